@@ -69,11 +69,14 @@ def jac_matrix(m, n, jrow, jcol, jval):
     return sp.csr_matrix((jval, (jrow, jcol)), shape=(m, n))
 
 
-def condensed_values(n, krow, kcol, hrow, hcol, hval, Jm, sigx, D, dw, hmag=None, jabs=None):
+def condensed_values(n, krow, kcol, hrow, hcol, hval, Jm, sigx, D, dw, hmag=None, jmag=None):
     """Values of K = W + dw I + Sx + J^T D J on the fixed pattern (krow, kcol).
 
-    If ``hmag``/``jabs`` are given also returns the magnitude
-    |W| + Sx + dw + |J|^T D |J| used to scale parity tolerances.
+    If ``hmag`` is given also returns the magnitude Wmag + Sx + dw + Jmag^T D Jmag
+    used to scale parity tolerances, where Wmag and Jmag (a sparse matrix with
+    the sparsity of J, default |J|) are the abs-sums of the product terms that
+    formed each Hessian and Jacobian entry: an entry formed with cancellation
+    carries rounding relative to its terms, not to its value.
     """
     W = sym_from_lower(n, hrow, hcol, hval)
     M = W + sp.diags(sigx + dw) + (Jm.T @ sp.diags(D) @ Jm)
@@ -82,7 +85,7 @@ def condensed_values(n, krow, kcol, hrow, hcol, hval, Jm, sigx, D, dw, hmag=None
     if hmag is None:
         return vals
     Wm = sym_from_lower(n, hrow, hcol, hmag)
-    Ja = abs(Jm)
+    Ja = abs(Jm) if jmag is None else jmag
     Mm = (Wm + sp.diags(np.abs(sigx) + abs(dw)) + (Ja.T @ sp.diags(np.abs(D)) @ Ja)).tocsr()
     mags = np.asarray(Mm[krow, kcol]).ravel()
     return vals, mags

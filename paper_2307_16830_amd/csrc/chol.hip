@@ -1,0 +1,833 @@
+// Pivot-free supernodal (multifrontal) Cholesky of the condensed matrix and
+// its triangular solves (Section IV-C: the condensed matrix is factored with a
+// fixed pivot sequence because it is positive definite once the inertia is
+// right).
+//
+// Numeric layout: supernode s owns a dense column-major front F_s of m_s x m_s
+// doubles (m_s = number of rows of the supernode, its n_s own columns first).
+// After the partial factorization the first n_s columns hold L's panel and
+// the trailing (m_s - n_s) block holds the update matrix passed to the parent.
+// Fronts are processed by elimination-tree level (leaves first); all fronts
+// of a level are independent and run in the same launches:
+//   * assembly: one work-group per 64x64 lower tile of a front gathers the
+//     entries of K that land in the tile and the children's update-matrix
+//     blocks that map into it (relative indices are monotone, so each child
+//     contributes one rectangle found by binary search).  No atomics: each
+//     tile is owned by one work-group.
+//   * fronts with m_s <= 64: the whole front lives in LDS, one work-group
+//     factors it (column Cholesky with the Schur update of the trailing block).
+//   * larger fronts: right-looking blocked partial factorization with 64-wide
+//     panels: diagonal-block Cholesky in LDS, panel triangular solve, and a
+//     trailing symmetric rank-64 update on FP64 MFMA (16x16x4) tiles.
+// The solves walk the levels upward (each front gathers its children's
+// partial results, solves with its diagonal block and forms its own partial
+// result for the parent) and then downward (each front gathers the already
+// computed solution at its off-diagonal rows).
+#include <algorithm>
+#include <climits>
+#include <cmath>
+
+#include "model.h"
+#include "symbolic.h"
+
+using namespace opf;
+
+struct chol_sym {
+    Symbolic S;
+    chol_options opts{};
+    int n = 0;
+    int64_t nnzk = 0;
+    int nlevels = 0;
+    int64_t front_total = 0, nnzl = 0, upd_total = 0;
+    double flops = 0;
+    bool factored = false;
+    // host mirrors
+    std::vector<int32_t> h_first, h_ncol, h_mrows, h_level;
+    std::vector<int64_t> h_foff, h_roff, h_uoff;
+    std::vector<int32_t> lvl_ptr, lvl_sn;           // supernodes by level
+    std::vector<int32_t> lvl_small_ptr, lvl_small;  // fronts with m <= 64 by level
+    // assembly tile work list (per level)
+    std::vector<int32_t> asm_ptr;                  // [nlevels+1] into tiles
+    // blocked steps: per (level, step) ranges into the three item lists
+    struct Step {
+        int level;
+        int32_t p0, p1, t0, t1, s0, s1;
+    };
+    std::vector<Step> steps;
+    std::vector<int32_t> lvl_step_ptr;
+    // device
+    DBuf<int32_t> first, ncol, mrows, perm;
+    DBuf<int64_t> foff, roff, uoff;
+    DBuf<int32_t> rows;
+    DBuf<int32_t> child_ptr, child;
+    DBuf<int64_t> rel_off;
+    DBuf<int32_t> rel;
+    DBuf<int32_t> tile_sn, tile_rc;  // tile work list: supernode, (tr << 16) | tc
+    DBuf<int64_t> tile_kptr;
+    DBuf<int32_t> tile_k, tile_kpos;
+    DBuf<int32_t> lvl_sn_d, lvl_small_d;
+    DBuf<int32_t> potrf_it, trsm_it, syrk_it;  // packed items
+    DBuf<int32_t> status;
+    DBuf<double> fronts, upd, work, ybuf;
+    Deferred dev;  // pending uploads, run at the first device use
+};
+
+namespace {
+
+constexpr int TB = 64;      // tile edge
+constexpr int NT = 256;     // threads per work-group
+
+__device__ __forceinline__ int lower_bound_dev(const int32_t* a, int n, int v) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (a[mid] < v)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------- assembly
+__global__ __launch_bounds__(NT) void front_assemble(int tile0, const int32_t* __restrict__ tile_sn,
+                                                     const int32_t* __restrict__ tile_rc,
+                                                     const int64_t* __restrict__ tile_kptr,
+                                                     const int32_t* __restrict__ tile_k,
+                                                     const int32_t* __restrict__ tile_kpos,
+                                                     const double* __restrict__ kval, const int32_t* __restrict__ ncol,
+                                                     const int32_t* __restrict__ mrows,
+                                                     const int64_t* __restrict__ foff,
+                                                     const int32_t* __restrict__ child_ptr,
+                                                     const int32_t* __restrict__ child,
+                                                     const int64_t* __restrict__ rel_off,
+                                                     const int32_t* __restrict__ rel, double* __restrict__ fronts) {
+    __shared__ double T[TB * TB];
+    const int item = tile0 + blockIdx.x;
+    const int s = tile_sn[item];
+    const int tr = tile_rc[item] >> 16, tc = tile_rc[item] & 0xffff;
+    const int m = mrows[s];
+    const int r0 = tr * TB, c0 = tc * TB;
+    for (int e = threadIdx.x; e < TB * TB; e += NT) T[e] = 0.0;
+    __syncthreads();
+    for (int64_t e = tile_kptr[item] + threadIdx.x; e < tile_kptr[item + 1]; e += NT) T[tile_kpos[e]] = kval[tile_k[e]];
+    __syncthreads();
+    for (int ci = child_ptr[s]; ci < child_ptr[s + 1]; ci++) {
+        const int c = child[ci];
+        const int nc = ncol[c], mc = mrows[c];
+        const int nu = mc - nc;
+        const int32_t* rl = rel + rel_off[c];
+        const int ra = lower_bound_dev(rl, nu, r0), rb = lower_bound_dev(rl, nu, r0 + TB);
+        const int ca = lower_bound_dev(rl, nu, c0), cb = lower_bound_dev(rl, nu, c0 + TB);
+        const int nr = rb - ra, ncc = cb - ca;
+        if (nr > 0 && ncc > 0) {
+            const double* F = fronts + foff[c];
+            for (int e = threadIdx.x; e < nr * ncc; e += NT) {
+                const int ui = ra + e % nr, uj = ca + e / nr;
+                if (ui >= uj) {
+                    const double u = F[(int64_t)(nc + ui) + (int64_t)mc * (nc + uj)];
+                    T[(rl[ui] - r0) + TB * (rl[uj] - c0)] += u;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    double* F = fronts + foff[s];
+    for (int e = threadIdx.x; e < TB * TB; e += NT) {
+        const int i = r0 + e % TB, j = c0 + e / TB;
+        if (i < m && j < m && i >= j) F[(int64_t)i + (int64_t)m * j] = T[e];
+    }
+}
+
+// ---------------------------------------------------------------- small fronts in LDS
+__device__ __forceinline__ void lds_cholesky(double* A, int lda, int m, int ncols, int* bad_local) {
+    // A: lower triangle, column-major in LDS.  Factors ncols pivot columns and
+    // applies their Schur update to the trailing (m - ncols) block.
+    const int ti = threadIdx.x % 64, tj = threadIdx.x / 64;
+    for (int k = 0; k < ncols; k++) {
+        __syncthreads();
+        double d = A[k + lda * k];
+        if (!(d > 0.0)) {
+            if (threadIdx.x == 0 && *bad_local < 0) *bad_local = k;
+            d = 1.0;
+        }
+        const double r = sqrt(d);
+        __syncthreads();
+        if (threadIdx.x == 0) A[k + lda * k] = r;
+        for (int i = k + 1 + threadIdx.x; i < m; i += NT) A[i + lda * k] /= r;
+        __syncthreads();
+        for (int j = k + 1 + tj; j < m; j += NT / 64)
+            for (int i = j + ti; i < m; i += 64) A[i + lda * j] -= A[i + lda * k] * A[j + lda * k];
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(NT) void front_small(const int32_t* __restrict__ list, const int32_t* __restrict__ first,
+                                                  const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
+                                                  const int64_t* __restrict__ foff, double* __restrict__ fronts,
+                                                  int32_t* __restrict__ status) {
+    __shared__ double A[TB * TB];
+    __shared__ int bad;
+    const int s = list[blockIdx.x];
+    const int m = mrows[s], nn = ncol[s];
+    double* F = fronts + foff[s];
+    if (threadIdx.x == 0) bad = -1;
+    for (int e = threadIdx.x; e < m * m; e += NT) {
+        const int i = e % m, j = e / m;
+        if (i >= j) A[i + TB * j] = F[e];
+    }
+    lds_cholesky(A, TB, m, nn, &bad);
+    for (int e = threadIdx.x; e < m * m; e += NT) {
+        const int i = e % m, j = e / m;
+        if (i >= j) F[e] = A[i + TB * j];
+    }
+    if (threadIdx.x == 0) status[s] = bad >= 0 ? first[s] + bad : INT_MAX;
+}
+
+// ---------------------------------------------------------------- blocked path for large fronts
+// items: potrf (s, k0) packed as two ints; trsm (s, k0, rb); syrk (s, k0, bi, bj)
+__global__ __launch_bounds__(NT) void blk_potrf(const int32_t* __restrict__ it, const int32_t* __restrict__ first,
+                                                const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
+                                                const int64_t* __restrict__ foff, double* __restrict__ fronts,
+                                                int32_t* __restrict__ status) {
+    __shared__ double A[TB * TB];
+    __shared__ int bad;
+    const int s = it[2 * blockIdx.x], k0 = it[2 * blockIdx.x + 1];
+    const int m = mrows[s];
+    const int kb = min(TB, ncol[s] - k0);
+    double* F = fronts + foff[s] + (int64_t)k0 + (int64_t)m * k0;
+    if (threadIdx.x == 0) bad = -1;
+    for (int e = threadIdx.x; e < kb * kb; e += NT) {
+        const int i = e % kb, j = e / kb;
+        if (i >= j) A[i + TB * j] = F[i + (int64_t)m * j];
+    }
+    lds_cholesky(A, TB, kb, kb, &bad);
+    for (int e = threadIdx.x; e < kb * kb; e += NT) {
+        const int i = e % kb, j = e / kb;
+        if (i >= j) F[i + (int64_t)m * j] = A[i + TB * j];
+    }
+    if (threadIdx.x == 0 && bad >= 0) status[s] = min(status[s], first[s] + k0 + bad);
+}
+
+// X <- X L_D^{-T} for a 64-row block of the panel below the diagonal block.
+__global__ __launch_bounds__(NT) void blk_trsm(const int32_t* __restrict__ it, const int32_t* __restrict__ ncol,
+                                               const int32_t* __restrict__ mrows, const int64_t* __restrict__ foff,
+                                               double* __restrict__ fronts) {
+    __shared__ double Ld[TB * TB];
+    __shared__ double X[TB * (TB + 1)];
+    const int s = it[3 * blockIdx.x], k0 = it[3 * blockIdx.x + 1], rb = it[3 * blockIdx.x + 2];
+    const int m = mrows[s];
+    const int kb = min(TB, ncol[s] - k0);
+    const int r0 = k0 + kb + rb * TB;
+    const int nr = min(TB, m - r0);
+    double* F = fronts + foff[s];
+    for (int e = threadIdx.x; e < kb * kb; e += NT) {
+        const int i = e % kb, j = e / kb;
+        if (i >= j) Ld[i + TB * j] = F[(int64_t)(k0 + i) + (int64_t)m * (k0 + j)];
+    }
+    for (int e = threadIdx.x; e < TB * kb; e += NT) {
+        const int i = e % TB, j = e / TB;
+        if (i < nr) X[i + (TB + 1) * j] = F[(int64_t)(r0 + i) + (int64_t)m * (k0 + j)];
+    }
+    __syncthreads();
+    // rows are independent: 4 threads per row split the inner products
+    const int row = threadIdx.x / 4, lane = threadIdx.x % 4;
+    for (int j = 0; j < kb; j++) {
+        double acc = 0.0;
+        if (row < nr)
+            for (int t = lane; t < j; t += 4) acc += X[row + (TB + 1) * t] * Ld[j + TB * t];
+        acc += __shfl_xor(acc, 1, 4);
+        acc += __shfl_xor(acc, 2, 4);
+        if (row < nr && lane == 0) X[row + (TB + 1) * j] = (X[row + (TB + 1) * j] - acc) / Ld[j + TB * j];
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < TB * kb; e += NT) {
+        const int i = e % TB, j = e / TB;
+        if (i < nr) F[(int64_t)(r0 + i) + (int64_t)m * (k0 + j)] = X[i + (TB + 1) * j];
+    }
+}
+
+// C(bi, bj) -= P_bi P_bj^T on the trailing matrix, FP64 MFMA 16x16x4.
+// Four waves; wave w computes the 32x32 quadrant (w / 2, w % 2) of the 64x64 tile
+// as 2x2 MFMA blocks of 16x16.
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(NT) void blk_syrk(const int32_t* __restrict__ it, const int32_t* __restrict__ ncol,
+                                               const int32_t* __restrict__ mrows, const int64_t* __restrict__ foff,
+                                               double* __restrict__ fronts) {
+    __shared__ double Pi[TB * (TB + 1)];
+    __shared__ double Pj[TB * (TB + 1)];
+    const int s = it[4 * blockIdx.x], k0 = it[4 * blockIdx.x + 1];
+    const int bi = it[4 * blockIdx.x + 2], bj = it[4 * blockIdx.x + 3];
+    const int m = mrows[s];
+    const int kb = min(TB, ncol[s] - k0);
+    const int base = k0 + kb;
+    const int ri0 = base + bi * TB, rj0 = base + bj * TB;
+    const int nri = min(TB, m - ri0), nrj = min(TB, m - rj0);
+    double* F = fronts + foff[s];
+    // stage the two panel blocks (rows x kb), zero-padded to 64 x 64
+    for (int e = threadIdx.x; e < TB * TB; e += NT) {
+        const int i = e % TB, t = e / TB;
+        double a = 0.0, b = 0.0;
+        if (t < kb) {
+            if (i < nri) a = F[(int64_t)(ri0 + i) + (int64_t)m * (k0 + t)];
+            if (i < nrj) b = F[(int64_t)(rj0 + i) + (int64_t)m * (k0 + t)];
+        }
+        Pi[i + (TB + 1) * t] = a;
+        Pj[i + (TB + 1) * t] = b;
+    }
+    __syncthreads();
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int qr = (wave / 2) * 32, qc = (wave % 2) * 32;
+    double4_t acc[2][2];
+    for (int a = 0; a < 2; a++)
+        for (int b = 0; b < 2; b++) acc[a][b] = double4_t{0.0, 0.0, 0.0, 0.0};
+    const int li = lane % 16, lk = lane / 16;
+    const int kbr = (kb + 3) & ~3;
+    for (int t = 0; t < kbr; t += 4) {
+        double av[2], bv[2];
+        for (int a = 0; a < 2; a++) av[a] = Pi[(qr + 16 * a + li) + (TB + 1) * (t + lk)];
+        for (int b = 0; b < 2; b++) bv[b] = Pj[(qc + 16 * b + li) + (TB + 1) * (t + lk)];
+        for (int a = 0; a < 2; a++)
+            for (int b = 0; b < 2; b++) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+    // D layout of the 16x16x4 f64 MFMA: item r of a lane is row (lane / 16) + 4 r, column lane % 16
+    for (int a = 0; a < 2; a++)
+        for (int b = 0; b < 2; b++)
+            for (int r = 0; r < 4; r++) {
+                const int i = qr + 16 * a + (lane / 16) + 4 * r;
+                const int j = qc + 16 * b + (lane % 16);
+                const int gi = ri0 + i, gj = rj0 + j;
+                if (i < nri && j < nrj && gi >= gj) F[(int64_t)gi + (int64_t)m * gj] -= acc[a][b][r];
+            }
+}
+
+// ---------------------------------------------------------------- solves
+__global__ void permute_in(int n, const int32_t* __restrict__ perm, const double* __restrict__ b,
+                           double* __restrict__ y) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) y[k] = b[perm[k]];
+}
+
+__global__ void permute_out(int n, const int32_t* __restrict__ perm, const double* __restrict__ y,
+                            double* __restrict__ x) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) x[perm[k]] = y[k];
+}
+
+// Forward sweep for one front: w = b(own rows) + children's partial results; solve with
+// the diagonal block; keep w on the off-diagonal rows as this front's partial result.
+__global__ __launch_bounds__(NT) void solve_fwd(const int32_t* __restrict__ list, const int32_t* __restrict__ first,
+                                                const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
+                                                const int64_t* __restrict__ foff, const int64_t* __restrict__ roff,
+                                                const int64_t* __restrict__ uoff,
+                                                const int32_t* __restrict__ child_ptr,
+                                                const int32_t* __restrict__ child,
+                                                const int64_t* __restrict__ rel_off, const int32_t* __restrict__ rel,
+                                                const double* __restrict__ fronts, double* __restrict__ work,
+                                                double* __restrict__ upd, double* __restrict__ y) {
+    const int s = list[blockIdx.x];
+    const int m = mrows[s], nn = ncol[s], f = first[s];
+    double* w = work + roff[s];
+    for (int t = threadIdx.x; t < m; t += NT) w[t] = t < nn ? y[f + t] : 0.0;
+    __syncthreads();
+    for (int ci = child_ptr[s]; ci < child_ptr[s + 1]; ci++) {
+        const int c = child[ci];
+        const int nu = mrows[c] - ncol[c];
+        const int32_t* rl = rel + rel_off[c];
+        const double* uc = upd + uoff[c];
+        for (int t = threadIdx.x; t < nu; t += NT) w[rl[t]] += uc[t];
+        __syncthreads();
+    }
+    const double* L = fronts + foff[s];
+    for (int j = 0; j < nn; j++) {
+        const double z = w[j] / L[j + (int64_t)m * j];
+        __syncthreads();
+        if (threadIdx.x == 0) w[j] = z;
+        for (int i = j + 1 + threadIdx.x; i < m; i += NT) w[i] -= L[i + (int64_t)m * j] * z;
+        __syncthreads();
+    }
+    for (int t = threadIdx.x; t < m; t += NT) {
+        if (t < nn)
+            y[f + t] = w[t];
+        else
+            upd[uoff[s] + (t - nn)] = w[t];
+    }
+}
+
+// Backward sweep for one front: x(own) = L11^{-T} (y(own) - L21^T x(rows below)).
+__global__ __launch_bounds__(NT) void solve_bwd(const int32_t* __restrict__ list, const int32_t* __restrict__ first,
+                                                const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
+                                                const int64_t* __restrict__ foff, const int64_t* __restrict__ roff,
+                                                const int32_t* __restrict__ rows, const double* __restrict__ fronts,
+                                                double* __restrict__ work, double* __restrict__ y) {
+    const int s = list[blockIdx.x];
+    const int m = mrows[s], nn = ncol[s], f = first[s];
+    const int32_t* R = rows + roff[s];
+    const double* L = fronts + foff[s];
+    double* w = work + roff[s];
+    for (int j = threadIdx.x; j < nn; j += NT) {
+        double acc = y[f + j];
+        const double* col = L + (int64_t)m * j;
+        for (int i = nn; i < m; i++) acc -= col[i] * y[R[i]];
+        w[j] = acc;
+    }
+    __syncthreads();
+    for (int j = nn - 1; j >= 0; j--) {
+        const double xj = w[j] / L[j + (int64_t)m * j];
+        __syncthreads();
+        if (threadIdx.x == 0) w[j] = xj;
+        for (int i = threadIdx.x; i < j; i += NT) w[i] -= L[j + (int64_t)m * i] * xj;
+        __syncthreads();
+    }
+    for (int j = threadIdx.x; j < nn; j += NT) y[f + j] = w[j];
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------ host side
+static void build_numeric_plan(chol_sym* C, const std::vector<int32_t>& colptr, const std::vector<int32_t>& rowind) {
+    const Symbolic& S = C->S;
+    const int ns = S.nsuper, n = S.n;
+    C->h_first.resize(ns);
+    C->h_ncol.resize(ns);
+    C->h_mrows.resize(ns);
+    C->h_foff.resize(ns + 1);
+    C->h_roff.resize(ns + 1);
+    C->h_uoff.resize(ns + 1);
+    int64_t fo = 0, uo = 0;
+    double flops = 0;
+    int64_t nnzl = 0;
+    for (int s = 0; s < ns; s++) {
+        int f = S.snode_ptr[s], nn = S.snode_ptr[s + 1] - f;
+        int64_t m = S.rows_ptr[s + 1] - S.rows_ptr[s];
+        C->h_first[s] = f;
+        C->h_ncol[s] = nn;
+        C->h_mrows[s] = (int32_t)m;
+        C->h_foff[s] = fo;
+        C->h_roff[s] = S.rows_ptr[s];
+        C->h_uoff[s] = uo;
+        fo += m * m;
+        uo += m - nn;
+        nnzl += (int64_t)nn * m - (int64_t)nn * (nn - 1) / 2;
+        for (int j = 0; j < nn; j++) {
+            double c = (double)(m - j);
+            flops += c * c;
+        }
+    }
+    C->h_foff[ns] = fo;
+    C->h_roff[ns] = S.rows_ptr[ns];
+    C->h_uoff[ns] = uo;
+    C->front_total = fo;
+    C->upd_total = uo;
+    C->nnzl = nnzl;
+    C->flops = flops;
+    // children lists and relative indices of each child's update rows in its parent
+    std::vector<int32_t> cptr(ns + 1, 0), clist;
+    for (int s = 0; s < ns; s++)
+        if (S.sparent[s] >= 0) cptr[S.sparent[s] + 1]++;
+    for (int s = 0; s < ns; s++) cptr[s + 1] += cptr[s];
+    clist.resize(cptr[ns]);
+    {
+        std::vector<int32_t> fill(cptr.begin(), cptr.end() - 1);
+        for (int s = 0; s < ns; s++)
+            if (S.sparent[s] >= 0) clist[fill[S.sparent[s]]++] = s;
+    }
+    std::vector<int64_t> reloff(ns + 1, 0);
+    std::vector<int32_t> rel;
+    std::vector<int32_t> pos(n, -1);
+    for (int s = 0; s < ns; s++) {
+        reloff[s] = (int64_t)rel.size();
+        int p = S.sparent[s];
+        int m = C->h_mrows[s], nn = C->h_ncol[s];
+        if (p < 0) continue;
+        const int32_t* Rp = S.rows_flat.data() + S.rows_ptr[p];
+        int mp = C->h_mrows[p];
+        for (int t = 0; t < mp; t++) pos[Rp[t]] = t;
+        const int32_t* Rs = S.rows_flat.data() + S.rows_ptr[s];
+        for (int t = nn; t < m; t++) rel.push_back(pos[Rs[t]]);
+        for (int t = 0; t < mp; t++) pos[Rp[t]] = -1;
+    }
+    reloff[ns] = (int64_t)rel.size();
+    // levels: height above the leaves
+    std::vector<int32_t> level(ns, 0);
+    for (int s = 0; s < ns; s++)
+        if (S.sparent[s] >= 0) level[S.sparent[s]] = std::max(level[S.sparent[s]], level[s] + 1);
+    int nl = 0;
+    for (int s = 0; s < ns; s++) nl = std::max(nl, level[s] + 1);
+    C->nlevels = nl;
+    C->h_level = level;
+    C->lvl_ptr.assign(nl + 1, 0);
+    for (int s = 0; s < ns; s++) C->lvl_ptr[level[s] + 1]++;
+    for (int l = 0; l < nl; l++) C->lvl_ptr[l + 1] += C->lvl_ptr[l];
+    C->lvl_sn.resize(ns);
+    {
+        std::vector<int32_t> fill(C->lvl_ptr.begin(), C->lvl_ptr.end() - 1);
+        for (int s = 0; s < ns; s++) C->lvl_sn[fill[level[s]]++] = s;
+    }
+    C->lvl_small_ptr.assign(nl + 1, 0);
+    C->lvl_small.clear();
+    // assembly tiles and K entries per tile
+    std::vector<int32_t> tsn, trc;
+    C->asm_ptr.assign(nl + 1, 0);
+    std::vector<int64_t> tile_of_front_start(ns, 0);
+    for (int l = 0; l < nl; l++) {
+        for (int q = C->lvl_ptr[l]; q < C->lvl_ptr[l + 1]; q++) {
+            int s = C->lvl_sn[q];
+            int m = C->h_mrows[s];
+            if (m <= TB) C->lvl_small.push_back(s);
+            int T = (m + TB - 1) / TB;
+            tile_of_front_start[s] = (int64_t)tsn.size();
+            for (int tc = 0; tc < T; tc++)
+                for (int tr = tc; tr < T; tr++) {
+                    tsn.push_back(s);
+                    trc.push_back((tr << 16) | tc);
+                }
+        }
+        C->lvl_small_ptr[l + 1] = (int32_t)C->lvl_small.size();
+        C->asm_ptr[l + 1] = (int32_t)tsn.size();
+    }
+    // K entry (original numbering, lower CSC) -> tile and in-tile position
+    const int64_t nk = rowind.size();
+    std::vector<int64_t> ktile(nk);
+    std::vector<int32_t> kpos(nk);
+    for (int jo = 0; jo < n; jo++) {
+        for (int p = colptr[jo]; p < colptr[jo + 1]; p++) {
+            int a = S.iperm[rowind[p]], b = S.iperm[jo];
+            int r = std::max(a, b), c = std::min(a, b);
+            int s = S.col2sn[c];
+            const int32_t* R = S.rows_flat.data() + S.rows_ptr[s];
+            int m = C->h_mrows[s], nn = C->h_ncol[s];
+            int lc = c - C->h_first[s];
+            int lr;
+            if (r - C->h_first[s] < nn)
+                lr = r - C->h_first[s];
+            else
+                lr = (int)(std::lower_bound(R + nn, R + m, r) - R);
+            int tr = lr / TB, tc = lc / TB;
+            int T = (m + TB - 1) / TB;
+            // tiles of a front are ordered by column then row (tr >= tc)
+            int64_t tidx = tile_of_front_start[s];
+            for (int cc = 0; cc < tc; cc++) tidx += T - cc;
+            tidx += tr - tc;
+            ktile[p] = tidx;
+            kpos[p] = (lr - tr * TB) + TB * (lc - tc * TB);
+        }
+    }
+    std::vector<int64_t> tkptr(tsn.size() + 1, 0);
+    for (int64_t p = 0; p < nk; p++) tkptr[ktile[p] + 1]++;
+    for (size_t t = 0; t < tsn.size(); t++) tkptr[t + 1] += tkptr[t];
+    std::vector<int32_t> tk(nk), tkpos(nk);
+    {
+        std::vector<int64_t> fill(tkptr.begin(), tkptr.end() - 1);
+        for (int64_t p = 0; p < nk; p++) {
+            int64_t q = fill[ktile[p]]++;
+            tk[q] = (int32_t)p;
+            tkpos[q] = kpos[p];
+        }
+    }
+    // blocked-path work lists per level and step for fronts with m > 64
+    std::vector<int32_t> pot, trs, syr;
+    C->steps.clear();
+    C->lvl_step_ptr.assign(nl + 1, 0);
+    for (int l = 0; l < nl; l++) {
+        int maxsteps = 0;
+        for (int q = C->lvl_ptr[l]; q < C->lvl_ptr[l + 1]; q++) {
+            int s = C->lvl_sn[q];
+            if (C->h_mrows[s] > TB) maxsteps = std::max(maxsteps, (C->h_ncol[s] + TB - 1) / TB);
+        }
+        for (int k = 0; k < maxsteps; k++) {
+            chol_sym::Step st{l, (int32_t)pot.size() / 2, 0, (int32_t)trs.size() / 3, 0, (int32_t)syr.size() / 4, 0};
+            for (int q = C->lvl_ptr[l]; q < C->lvl_ptr[l + 1]; q++) {
+                int s = C->lvl_sn[q];
+                int m = C->h_mrows[s], nn = C->h_ncol[s];
+                if (m <= TB) continue;
+                int k0 = k * TB;
+                if (k0 >= nn) continue;
+                int kb = std::min(TB, nn - k0);
+                pot.push_back(s);
+                pot.push_back(k0);
+                int rest = m - k0 - kb;
+                int T = (rest + TB - 1) / TB;
+                for (int rb = 0; rb < T; rb++) {
+                    trs.push_back(s);
+                    trs.push_back(k0);
+                    trs.push_back(rb);
+                }
+                for (int bj = 0; bj < T; bj++)
+                    for (int bi = bj; bi < T; bi++) {
+                        syr.push_back(s);
+                        syr.push_back(k0);
+                        syr.push_back(bi);
+                        syr.push_back(bj);
+                    }
+            }
+            st.p1 = (int32_t)pot.size() / 2;
+            st.t1 = (int32_t)trs.size() / 3;
+            st.s1 = (int32_t)syr.size() / 4;
+            C->steps.push_back(st);
+        }
+        C->lvl_step_ptr[l + 1] = (int32_t)C->steps.size();
+    }
+    // upload
+    C->dev.upload(C->first, C->h_first);
+    C->dev.upload(C->ncol, C->h_ncol);
+    C->dev.upload(C->mrows, C->h_mrows);
+    C->dev.upload(C->perm, S.perm);
+    C->dev.upload(C->foff, C->h_foff);
+    C->dev.upload(C->roff, C->h_roff);
+    C->dev.upload(C->uoff, C->h_uoff);
+    C->dev.upload(C->rows, S.rows_flat);
+    C->dev.upload(C->child_ptr, cptr);
+    C->dev.upload(C->child, clist);
+    C->dev.upload(C->rel_off, reloff);
+    C->dev.upload(C->rel, rel);
+    C->dev.upload(C->tile_sn, tsn);
+    C->dev.upload(C->tile_rc, trc);
+    C->dev.upload(C->tile_kptr, tkptr);
+    C->dev.upload(C->tile_k, tk);
+    C->dev.upload(C->tile_kpos, tkpos);
+    C->dev.upload(C->lvl_sn_d, C->lvl_sn);
+    C->dev.upload(C->lvl_small_d, C->lvl_small);
+    C->dev.upload(C->potrf_it, pot);
+    C->dev.upload(C->trsm_it, trs);
+    C->dev.upload(C->syrk_it, syr);
+    C->dev.alloc(C->status, std::max(ns, 1));
+    C->dev.alloc(C->fronts, std::max<int64_t>(fo, 1));
+    C->dev.alloc(C->upd, std::max<int64_t>(uo, 1));
+    C->dev.alloc(C->work, std::max<int64_t>(C->h_roff[ns], 1));
+    C->dev.alloc(C->ybuf, std::max(n, 1));
+}
+
+extern "C" void chol_default_options(chol_options* o) {
+    o->dense_frac = 0.5;
+    o->dense_abs = INT32_MAX;
+    o->max_width = INT32_MAX;
+    o->zero_abs = 64;
+    o->zero_rel = 0.05;
+}
+
+extern "C" int chol_analyze(int32_t n, const int32_t* colptr, const int32_t* rowind, const chol_options* opts,
+                            chol_sym** out) {
+    return guarded([&] {
+        OPF_CHECK(out && colptr && rowind && n >= 1, OPF_E_INVALID, "chol_analyze: bad argument");
+        *out = nullptr;
+        std::vector<int32_t> cp(colptr, colptr + n + 1);
+        OPF_CHECK(cp[0] == 0, OPF_E_INVALID, "chol_analyze: colptr[0] must be 0");
+        for (int j = 0; j < n; j++) OPF_CHECK(cp[j + 1] >= cp[j], OPF_E_INVALID, "chol_analyze: colptr not monotone");
+        std::vector<int32_t> ri(rowind, rowind + cp[n]);
+        for (int j = 0; j < n; j++) {
+            bool diag = false;
+            for (int p = cp[j]; p < cp[j + 1]; p++) {
+                OPF_CHECK(ri[p] >= j && ri[p] < n, OPF_E_INVALID, "chol_analyze: entry (%d,%d) not in the lower triangle",
+                          ri[p], j);
+                OPF_CHECK(p == cp[j] || ri[p] > ri[p - 1], OPF_E_INVALID, "chol_analyze: rows not strictly ascending");
+                diag |= ri[p] == j;
+            }
+            OPF_CHECK(diag, OPF_E_INVALID, "chol_analyze: column %d has no diagonal entry", j);
+        }
+        chol_options o;
+        chol_default_options(&o);
+        if (opts) o = *opts;
+        auto* C = new chol_sym();
+        try {
+            C->opts = o;
+            C->n = n;
+            C->nnzk = cp[n];
+            C->S = analyze_pattern(n, cp, ri, o);
+            build_numeric_plan(C, cp, ri);
+        } catch (...) {
+            delete C;
+            throw;
+        }
+        *out = C;
+    });
+}
+
+extern "C" int chol_destroy(chol_sym* C) {
+    delete C;
+    return OPF_OK;
+}
+
+extern "C" int chol_info(const chol_sym* C, int32_t* nsuper, int64_t* nnz_l, double* flops, int64_t* factor_bytes) {
+    return guarded([&] {
+        OPF_CHECK(C, OPF_E_INVALID, "chol_info: null handle");
+        if (nsuper) *nsuper = C->S.nsuper;
+        if (nnz_l) *nnz_l = C->nnzl;
+        if (flops) *flops = C->flops;
+        if (factor_bytes) *factor_bytes = C->front_total * 8;
+    });
+}
+
+extern "C" int chol_perm(const chol_sym* C, int32_t* perm) {
+    return guarded([&] {
+        OPF_CHECK(C && perm, OPF_E_INVALID, "chol_perm: null argument");
+        memcpy(perm, C->S.perm.data(), C->S.perm.size() * 4);
+    });
+}
+
+extern "C" int chol_etree(const chol_sym* C, int32_t* parent, int32_t* colcount) {
+    return guarded([&] {
+        OPF_CHECK(C, OPF_E_INVALID, "chol_etree: null handle");
+        if (parent) memcpy(parent, C->S.parent.data(), C->S.parent.size() * 4);
+        if (colcount) memcpy(colcount, C->S.colcount.data(), C->S.colcount.size() * 4);
+    });
+}
+
+extern "C" int chol_supernodes(const chol_sym* C, int32_t* snode_ptr) {
+    return guarded([&] {
+        OPF_CHECK(C && snode_ptr, OPF_E_INVALID, "chol_supernodes: null argument");
+        memcpy(snode_ptr, C->S.snode_ptr.data(), C->S.snode_ptr.size() * 4);
+    });
+}
+
+extern "C" int chol_supernode_rows(const chol_sym* C, int64_t* rows_ptr, int32_t* rows) {
+    return guarded([&] {
+        OPF_CHECK(C, OPF_E_INVALID, "chol_supernode_rows: null handle");
+        if (rows_ptr) memcpy(rows_ptr, C->S.rows_ptr.data(), C->S.rows_ptr.size() * 8);
+        if (rows) memcpy(rows, C->S.rows_flat.data(), C->S.rows_flat.size() * 4);
+    });
+}
+
+namespace opf {
+
+// Enqueue the numeric factorization (no synchronisation).
+void chol_factor_enqueue(chol_sym* C, const double* kval, hipStream_t st) {
+    C->dev.run();
+    for (int l = 0; l < C->nlevels; l++) {
+        int t0 = C->asm_ptr[l], t1 = C->asm_ptr[l + 1];
+        if (t1 > t0) {
+            hipLaunchKernelGGL(front_assemble, dim3(t1 - t0), dim3(NT), 0, st, t0, C->tile_sn.p, C->tile_rc.p,
+                               C->tile_kptr.p, C->tile_k.p, C->tile_kpos.p, kval, C->ncol.p, C->mrows.p, C->foff.p,
+                               C->child_ptr.p, C->child.p, C->rel_off.p, C->rel.p, C->fronts.p);
+            OPF_LAUNCH_CHECK();
+        }
+        int s0 = C->lvl_small_ptr[l], s1 = C->lvl_small_ptr[l + 1];
+        if (s1 > s0) {
+            hipLaunchKernelGGL(front_small, dim3(s1 - s0), dim3(NT), 0, st, C->lvl_small_d.p + s0, C->first.p,
+                               C->ncol.p, C->mrows.p, C->foff.p, C->fronts.p, C->status.p);
+            OPF_LAUNCH_CHECK();
+        }
+        for (int q = C->lvl_step_ptr[l]; q < C->lvl_step_ptr[l + 1]; q++) {
+            const chol_sym::Step& S = C->steps[q];
+            if (S.p1 > S.p0) {
+                hipLaunchKernelGGL(blk_potrf, dim3(S.p1 - S.p0), dim3(NT), 0, st, C->potrf_it.p + 2 * S.p0,
+                                   C->first.p, C->ncol.p, C->mrows.p, C->foff.p, C->fronts.p, C->status.p);
+                OPF_LAUNCH_CHECK();
+            }
+            if (S.t1 > S.t0) {
+                hipLaunchKernelGGL(blk_trsm, dim3(S.t1 - S.t0), dim3(NT), 0, st, C->trsm_it.p + 3 * S.t0, C->ncol.p,
+                                   C->mrows.p, C->foff.p, C->fronts.p);
+                OPF_LAUNCH_CHECK();
+            }
+            if (S.s1 > S.s0) {
+                hipLaunchKernelGGL(blk_syrk, dim3(S.s1 - S.s0), dim3(NT), 0, st, C->syrk_it.p + 4 * S.s0, C->ncol.p,
+                                   C->mrows.p, C->foff.p, C->fronts.p);
+                OPF_LAUNCH_CHECK();
+            }
+        }
+    }
+}
+
+__global__ void init_status(int ns, const int32_t* __restrict__ mrows, int32_t* __restrict__ status) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < ns && mrows[s] > TB) status[s] = INT_MAX;
+}
+
+// Factor and report: returns -1 if positive definite, else the bad pivot.
+int chol_factor_sync(chol_sym* C, const double* kval, hipStream_t st) {
+    C->dev.run();
+    const int ns = C->S.nsuper;
+    hipLaunchKernelGGL(init_status, dim3(ceil_div(ns, 256)), dim3(256), 0, st, ns, C->mrows.p, C->status.p);
+    OPF_LAUNCH_CHECK();
+    chol_factor_enqueue(C, kval, st);
+    std::vector<int32_t> stat(ns);
+    OPF_HIP(hipMemcpyAsync(stat.data(), C->status.p, ns * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    OPF_HIP(hipStreamSynchronize(st));
+    int bad_level = INT_MAX, bad = -1;
+    for (int s = 0; s < ns; s++)
+        if (stat[s] != INT_MAX) {
+            int l = C->h_level[s];
+            if (l < bad_level || (l == bad_level && stat[s] < bad)) {
+                bad_level = l;
+                bad = stat[s];
+            }
+        }
+    C->factored = bad < 0;
+    return bad;
+}
+
+void chol_solve_enqueue(chol_sym* C, const double* b, double* x, hipStream_t st) {
+    C->dev.run();
+    const int n = C->n;
+    double* y = C->ybuf.p;
+    hipLaunchKernelGGL(permute_in, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, C->perm.p, b, y);
+    OPF_LAUNCH_CHECK();
+    for (int l = 0; l < C->nlevels; l++) {
+        int q0 = C->lvl_ptr[l], q1 = C->lvl_ptr[l + 1];
+        hipLaunchKernelGGL(solve_fwd, dim3(q1 - q0), dim3(NT), 0, st, C->lvl_sn_d.p + q0, C->first.p, C->ncol.p,
+                           C->mrows.p, C->foff.p, C->roff.p, C->uoff.p, C->child_ptr.p, C->child.p, C->rel_off.p,
+                           C->rel.p, C->fronts.p, C->work.p, C->upd.p, y);
+        OPF_LAUNCH_CHECK();
+    }
+    for (int l = C->nlevels - 1; l >= 0; l--) {
+        int q0 = C->lvl_ptr[l], q1 = C->lvl_ptr[l + 1];
+        hipLaunchKernelGGL(solve_bwd, dim3(q1 - q0), dim3(NT), 0, st, C->lvl_sn_d.p + q0, C->first.p, C->ncol.p,
+                           C->mrows.p, C->foff.p, C->roff.p, C->rows.p, C->fronts.p, C->work.p, y);
+        OPF_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(permute_out, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, C->perm.p, y, x);
+    OPF_LAUNCH_CHECK();
+}
+
+}  // namespace opf
+
+extern "C" int chol_factor(chol_sym* C, const double* kval, void* stream, int32_t* bad_col) {
+    return guarded([&] {
+        OPF_CHECK(C && kval, OPF_E_INVALID, "chol_factor: null argument");
+        int bad = chol_factor_sync(C, kval, (hipStream_t)stream);
+        if (bad_col) *bad_col = bad;
+        if (bad >= 0) {
+            set_error("chol_factor: non-positive pivot at pivot index %d", bad);
+            throw Error{OPF_E_NOT_PD};
+        }
+    });
+}
+
+extern "C" int chol_solve(chol_sym* C, const double* b, double* x, int32_t nrhs, void* stream) {
+    return guarded([&] {
+        OPF_CHECK(C && b && x && nrhs >= 0, OPF_E_INVALID, "chol_solve: bad argument");
+        OPF_CHECK(C->factored, OPF_E_STATE, "chol_solve: no successful factorization");
+        for (int r = 0; r < nrhs; r++)
+            chol_solve_enqueue(C, b + (int64_t)r * C->n, x + (int64_t)r * C->n, (hipStream_t)stream);
+    });
+}
+
+extern "C" int chol_export_factor(chol_sym* C, int64_t* lp, int32_t* li, double* lx) {
+    return guarded([&] {
+        OPF_CHECK(C && lp && li, OPF_E_INVALID, "chol_export_factor: null argument");
+        std::vector<double> F;
+        if (lx) {
+            OPF_CHECK(C->factored, OPF_E_STATE, "chol_export_factor: no successful factorization");
+            C->dev.run();
+            F.resize(C->front_total);
+            OPF_HIP(hipDeviceSynchronize());
+            OPF_HIP(hipMemcpy(F.data(), C->fronts.p, C->front_total * 8, hipMemcpyDeviceToHost));
+        }
+        const Symbolic& S = C->S;
+        int64_t q = 0;
+        lp[0] = 0;
+        for (int s = 0; s < S.nsuper; s++) {
+            int f = C->h_first[s], nn = C->h_ncol[s], m = C->h_mrows[s];
+            const int32_t* R = S.rows_flat.data() + S.rows_ptr[s];
+            for (int jc = 0; jc < nn; jc++) {
+                for (int jr = jc; jr < m; jr++) {
+                    li[q] = R[jr];
+                    if (lx) lx[q] = F[C->h_foff[s] + jr + (int64_t)m * jc];
+                    q++;
+                }
+                lp[f + jc + 1] = q;
+            }
+        }
+    });
+}

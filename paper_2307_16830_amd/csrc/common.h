@@ -1,0 +1,134 @@
+// Shared internals of libopf: error reporting, device buffers, launch helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <string>
+#include <vector>
+
+#include "opf.h"
+
+namespace opf {
+
+void set_error(const char* fmt, ...);
+
+// Returned through the C ABI as an opf_status.
+struct Error {
+    int code;
+};
+
+#define OPF_HIP(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) {                                                              \
+            ::opf::set_error("%s:%d: %s: %s", __FILE__, __LINE__, #expr, hipGetErrorString(e_)); \
+            throw ::opf::Error{OPF_E_DEVICE};                                                \
+        }                                                                                    \
+    } while (0)
+
+#define OPF_CHECK(cond, code, ...)           \
+    do {                                     \
+        if (!(cond)) {                       \
+            ::opf::set_error(__VA_ARGS__);   \
+            throw ::opf::Error{code};        \
+        }                                    \
+    } while (0)
+
+#define OPF_LAUNCH_CHECK() OPF_HIP(hipGetLastError())
+
+// Run a body that may throw opf::Error / std::bad_alloc and map to a status.
+template <class F>
+int guarded(F&& f) {
+    try {
+        f();
+        return OPF_OK;
+    } catch (const Error& e) {
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_error("host allocation failed");
+        return OPF_E_NOMEM;
+    } catch (...) {
+        set_error("unexpected C++ exception");
+        return OPF_E_INVALID;
+    }
+}
+
+// Owning HBM buffer.
+template <class T>
+struct DBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    DBuf() = default;
+    explicit DBuf(size_t count) { alloc(count); }
+    DBuf(const DBuf&) = delete;
+    DBuf& operator=(const DBuf&) = delete;
+    DBuf(DBuf&& o) noexcept : p(o.p), n(o.n) {
+        o.p = nullptr;
+        o.n = 0;
+    }
+    DBuf& operator=(DBuf&& o) noexcept {
+        if (this != &o) {
+            release();
+            p = o.p;
+            n = o.n;
+            o.p = nullptr;
+            o.n = 0;
+        }
+        return *this;
+    }
+    ~DBuf() { release(); }
+    void alloc(size_t count) {
+        release();
+        n = count;
+        if (count == 0) return;
+        hipError_t e = hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T));
+        if (e != hipSuccess) {
+            p = nullptr;
+            n = 0;
+            set_error("hipMalloc of %zu bytes failed: %s", count * sizeof(T), hipGetErrorString(e));
+            throw Error{OPF_E_NOMEM};
+        }
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    void upload(const std::vector<T>& h, hipStream_t s = nullptr) {
+        alloc(h.size());
+        if (!h.empty()) {
+            OPF_HIP(hipMemcpyAsync(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+            OPF_HIP(hipStreamSynchronize(s));
+        }
+    }
+};
+
+// Device uploads recorded on the host and performed at the first device use,
+// so that host-only queries (structure, patterns, symbolic analysis) work
+// without touching the GPU.
+struct Deferred {
+    std::vector<std::function<void()>> jobs;
+    bool done = false;
+    template <class T>
+    void upload(DBuf<T>& d, std::vector<T> h) {
+        jobs.push_back([&d, h = std::move(h)]() { d.upload(h); });
+    }
+    template <class T>
+    void alloc(DBuf<T>& d, size_t n) {
+        jobs.push_back([&d, n]() { d.alloc(n); });
+    }
+    void run() {
+        if (done) return;
+        for (auto& j : jobs) j();
+        jobs.clear();
+        done = true;
+    }
+};
+
+inline unsigned ceil_div(size_t a, size_t b) { return static_cast<unsigned>((a + b - 1) / b); }
+
+}  // namespace opf
