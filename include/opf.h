@@ -141,6 +141,9 @@ typedef struct {
     int32_t max_width; /* default INT32_MAX */
     int64_t zero_abs;  /* default 64 */
     double zero_rel;   /* default 0.05 */
+    /* numeric: a pivot is accepted when it exceeds pivot_tol * |K_jj| (the
+     * assembled diagonal entry); default 0, i.e. when it is positive */
+    double pivot_tol;
 } chol_options;
 
 typedef struct chol_sym chol_sym;
@@ -164,9 +167,10 @@ int chol_supernodes(const chol_sym* sym, int32_t* snode_ptr);
 int chol_supernode_rows(const chol_sym* sym, int64_t* rows_ptr, int32_t* rows);
 /* Numeric factorization of P K P^T = L L^T from device values kval [nnz]
  * in the analyzed pattern's order.  Synchronises the stream; returns
- * OPF_E_NOT_PD and *bad_col = pivot index of the first non-positive pivot
- * found (a smallest such index within the first failing elimination level),
- * else OPF_OK and *bad_col = -1.  The factor stays in HBM. */
+ * OPF_E_NOT_PD and *bad_col = pivot index of the first rejected pivot
+ * (see pivot_tol; the smallest such index within the first failing
+ * elimination level), else OPF_OK and *bad_col = -1.  The factor stays in
+ * HBM. */
 int chol_factor(chol_sym* sym, const double* kval, void* stream, int32_t* bad_col);
 /* x = K^{-1} b using the last successful factor; b, x device [n*nrhs]
  * (column-major, leading dimension n; x may alias b).  Asynchronous. */
@@ -193,6 +197,7 @@ typedef struct {
     double ir_tol;     /* default 1e-10 */
     double mu_init;    /* default 0.1 */
     double bound_relax;/* default 1e-8 */
+    double pivot_tol;  /* pivot acceptance of the factorizations, default 1e-12 (see chol_options) */
 } ipm_options;
 
 typedef struct {

@@ -35,7 +35,7 @@ def lib():
         L.oracle_chol_nnz.argtypes = [ctypes.c_void_p]
         L.oracle_chol_nnz.restype = ctypes.c_int64
         L.oracle_chol_export.argtypes = [ctypes.c_void_p, I32P, I32P, F64P]
-        L.oracle_chol_factor.argtypes = [ctypes.c_void_p, F64P]
+        L.oracle_chol_factor.argtypes = [ctypes.c_void_p, F64P, ctypes.c_double]
         L.oracle_chol_factor.restype = ctypes.c_int
         L.oracle_chol_solve.argtypes = [ctypes.c_void_p, F64P, F64P]
         _lib = L
@@ -58,7 +58,7 @@ class AnalyzeOptions:
 
     dense_frac: float = 0.5
     dense_abs: int = 2 ** 31 - 1
-    max_width: int = 64
+    max_width: int = 2 ** 31 - 1
     zero_abs: int = 64
     zero_rel: float = 0.05
 
@@ -134,11 +134,12 @@ class Cholesky:
     def nnz(self):
         return int(lib().oracle_chol_nnz(self._h))
 
-    def factor(self, values):
-        """Returns -1 if positive definite, else the first failing pivot column (permuted numbering)."""
+    def factor(self, values, piv_tol=0.0):
+        """Returns -1 if every pivot exceeds piv_tol * |K_jj| (0: positive definite), else the first
+        failing pivot column (permuted numbering)."""
         v, vp = _f64(values)
         assert v.shape[0] == self._ri.shape[0]
-        rc = lib().oracle_chol_factor(self._h, vp)
+        rc = lib().oracle_chol_factor(self._h, vp, float(piv_tol))
         if rc < 0:
             raise MemoryError("oracle_chol_factor failed")
         return -1 if rc == 0 else rc - 1

@@ -627,10 +627,11 @@ void oracle_chol_export(const oracle_chol* f, i32* lp, i32* li, double* lx) {
 
 /*
  * Numeric factorization of P K P^T where K has the pattern given at create
- * time and values val (same CSC order).  Returns 0 if positive definite,
- * else (1 + j) for the first pivot column j whose pivot is not positive.
+ * time and values val (same CSC order).  A pivot is accepted when it exceeds
+ * piv_tol * |A(j,j)| (piv_tol = 0: when it is positive).  Returns 0 if every
+ * pivot is accepted, else (1 + j) for the first pivot column j that is not.
  */
-int oracle_chol_factor(oracle_chol* f, const double* val) {
+int oracle_chol_factor(oracle_chol* f, const double* val, double piv_tol) {
     i32 n = f->n;
     i32 nnz = f->bptr[n];
     double* w = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
@@ -654,7 +655,8 @@ int oracle_chol_factor(oracle_chol* f, const double* val) {
             for (i32 p = pj; p < f->lp[k + 1]; p++) w[f->li[p]] -= f->lx[p] * ljk;
         }
         double d = w[j];
-        if (!(d > 0.0)) {
+        double ajj = bv[f->bptr[j]]; /* diagonal entry: first row of column j */
+        if (!(d > piv_tol * fabs(ajj))) {
             status = 1 + j;
             for (i32 p = f->lp[j]; p < f->lp[j + 1]; p++) w[f->li[p]] = 0.0;
             break;

@@ -63,6 +63,9 @@ class Options:
     max_ir: int = 10
     ir_tol: float = 1e-10
     ir_stall: float = 0.9
+    # a pivot counts as positive only above pivot_tol * |K_jj|: at that size its sign is within
+    # rounding noise of the condensed matrix, so regularization is applied instead
+    pivot_tol: float = 1e-12
 
 
 class Status:
@@ -269,7 +272,7 @@ class IPM:
             return v
 
         dw = 0.0
-        bad = self.chol.factor(kvals(dw))
+        bad = self.chol.factor(kvals(dw), o.pivot_tol)
         trials += 1
         if bad < 0:
             return dw, trials
@@ -277,7 +280,7 @@ class IPM:
         while True:
             if dw > o.dw_max:
                 return None, trials
-            bad = self.chol.factor(kvals(dw))
+            bad = self.chol.factor(kvals(dw), o.pivot_tol)
             trials += 1
             if bad < 0:
                 self.dw_last = dw

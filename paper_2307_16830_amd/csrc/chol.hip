@@ -46,6 +46,8 @@ struct chol_sym {
     std::vector<int64_t> h_foff, h_roff, h_uoff;
     std::vector<int32_t> lvl_ptr, lvl_sn;           // supernodes by level
     std::vector<int32_t> lvl_small_ptr, lvl_small;  // fronts with m <= 64 by level
+    std::vector<int32_t> lvl_narrow_ptr, lvl_narrow;  // fronts solved by one work-group, by level
+    std::vector<int32_t> lvl_wide_ptr, lvl_wide;      // fronts with >= WIDE pivots, by level
     // assembly tile work list (per level)
     std::vector<int32_t> asm_ptr;                  // [nlevels+1] into tiles
     // blocked steps: per (level, step) ranges into the three item lists
@@ -57,6 +59,7 @@ struct chol_sym {
     std::vector<int32_t> lvl_step_ptr;
     // device
     DBuf<int32_t> first, ncol, mrows, perm;
+    DBuf<int32_t> kdiagpos;  // pivot -> position of its diagonal entry in K's values
     DBuf<int64_t> foff, roff, uoff;
     DBuf<int32_t> rows;
     DBuf<int32_t> child_ptr, child;
@@ -65,7 +68,7 @@ struct chol_sym {
     DBuf<int32_t> tile_sn, tile_rc;  // tile work list: supernode, (tr << 16) | tc
     DBuf<int64_t> tile_kptr;
     DBuf<int32_t> tile_k, tile_kpos;
-    DBuf<int32_t> lvl_sn_d, lvl_small_d;
+    DBuf<int32_t> lvl_sn_d, lvl_small_d, lvl_narrow_d, lvl_wide_d;
     DBuf<int32_t> potrf_it, trsm_it, syrk_it;  // packed items
     DBuf<int32_t> status;
     DBuf<double> fronts, upd, work, ybuf;
@@ -140,14 +143,25 @@ __global__ __launch_bounds__(NT) void front_assemble(int tile0, const int32_t* _
 }
 
 // ---------------------------------------------------------------- small fronts in LDS
-__device__ __forceinline__ void lds_cholesky(double* A, int lda, int m, int ncols, int* bad_local) {
+// A pivot is accepted when it exceeds tol * |K_jj| (tol = 0: when it is positive).
+struct PivotRef {
+    const double* kval;
+    const int32_t* kdiagpos;
+    double tol;
+    __device__ __forceinline__ double thresh(int pivot) const {
+        return tol > 0.0 ? tol * fabs(kval[kdiagpos[pivot]]) : 0.0;
+    }
+};
+
+__device__ __forceinline__ void lds_cholesky(double* A, int lda, int m, int ncols, int* bad_local, PivotRef pr,
+                                             int pivot0) {
     // A: lower triangle, column-major in LDS.  Factors ncols pivot columns and
     // applies their Schur update to the trailing (m - ncols) block.
     const int ti = threadIdx.x % 64, tj = threadIdx.x / 64;
     for (int k = 0; k < ncols; k++) {
         __syncthreads();
         double d = A[k + lda * k];
-        if (!(d > 0.0)) {
+        if (!(d > pr.thresh(pivot0 + k))) {
             if (threadIdx.x == 0 && *bad_local < 0) *bad_local = k;
             d = 1.0;
         }
@@ -165,7 +179,7 @@ __device__ __forceinline__ void lds_cholesky(double* A, int lda, int m, int ncol
 __global__ __launch_bounds__(NT) void front_small(const int32_t* __restrict__ list, const int32_t* __restrict__ first,
                                                   const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
                                                   const int64_t* __restrict__ foff, double* __restrict__ fronts,
-                                                  int32_t* __restrict__ status) {
+                                                  int32_t* __restrict__ status, PivotRef pr) {
     __shared__ double A[TB * TB];
     __shared__ int bad;
     const int s = list[blockIdx.x];
@@ -176,7 +190,7 @@ __global__ __launch_bounds__(NT) void front_small(const int32_t* __restrict__ li
         const int i = e % m, j = e / m;
         if (i >= j) A[i + TB * j] = F[e];
     }
-    lds_cholesky(A, TB, m, nn, &bad);
+    lds_cholesky(A, TB, m, nn, &bad, pr, first[s]);
     for (int e = threadIdx.x; e < m * m; e += NT) {
         const int i = e % m, j = e / m;
         if (i >= j) F[e] = A[i + TB * j];
@@ -186,119 +200,154 @@ __global__ __launch_bounds__(NT) void front_small(const int32_t* __restrict__ li
 
 // ---------------------------------------------------------------- blocked path for large fronts
 // items: potrf (s, k0) packed as two ints; trsm (s, k0, rb); syrk (s, k0, bi, bj)
-__global__ __launch_bounds__(NT) void blk_potrf(const int32_t* __restrict__ it, const int32_t* __restrict__ first,
+constexpr int ST = 128;  // trailing-update tile edge
+
+// Cholesky of the kb x kb diagonal block at (k0, k0): one wave, LDS row-major, lane i owns row i.
+__global__ __launch_bounds__(64) void blk_potrf(const int32_t* __restrict__ it, const int32_t* __restrict__ first,
                                                 const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
                                                 const int64_t* __restrict__ foff, double* __restrict__ fronts,
-                                                int32_t* __restrict__ status) {
-    __shared__ double A[TB * TB];
-    __shared__ int bad;
+                                                int32_t* __restrict__ status, PivotRef pr) {
+    __shared__ double A[TB * (TB + 1)];
     const int s = it[2 * blockIdx.x], k0 = it[2 * blockIdx.x + 1];
     const int m = mrows[s];
     const int kb = min(TB, ncol[s] - k0);
     double* F = fronts + foff[s] + (int64_t)k0 + (int64_t)m * k0;
-    if (threadIdx.x == 0) bad = -1;
-    for (int e = threadIdx.x; e < kb * kb; e += NT) {
-        const int i = e % kb, j = e / kb;
-        if (i >= j) A[i + TB * j] = F[i + (int64_t)m * j];
+    const int i = threadIdx.x;
+    for (int e = i; e < kb * kb; e += 64) {
+        const int r = e % kb, c = e / kb;
+        if (r >= c) A[r * (TB + 1) + c] = F[r + (int64_t)m * c];
     }
-    lds_cholesky(A, TB, kb, kb, &bad);
-    for (int e = threadIdx.x; e < kb * kb; e += NT) {
-        const int i = e % kb, j = e / kb;
-        if (i >= j) F[i + (int64_t)m * j] = A[i + TB * j];
+    __syncthreads();
+    int bad = -1;
+    for (int k = 0; k < kb; k++) {
+        double d = A[k * (TB + 1) + k];
+        if (!(d > pr.thresh(first[s] + k0 + k))) {
+            if (bad < 0) bad = k;
+            d = 1.0;
+        }
+        const double r = sqrt(d);
+        __syncthreads();
+        if (i == k) A[k * (TB + 1) + k] = r;
+        if (i > k && i < kb) A[i * (TB + 1) + k] /= r;
+        __syncthreads();
+        if (i > k && i < kb) {
+            const double lik = A[i * (TB + 1) + k];
+            for (int j = k + 1; j <= i; j++) A[i * (TB + 1) + j] -= lik * A[j * (TB + 1) + k];
+        }
+        __syncthreads();
     }
-    if (threadIdx.x == 0 && bad >= 0) status[s] = min(status[s], first[s] + k0 + bad);
+    for (int e = i; e < kb * kb; e += 64) {
+        const int r = e % kb, c = e / kb;
+        if (r >= c) F[r + (int64_t)m * c] = A[r * (TB + 1) + c];
+    }
+    if (i == 0 && bad >= 0) status[s] = min(status[s], first[s] + k0 + bad);
 }
 
-// X <- X L_D^{-T} for a 64-row block of the panel below the diagonal block.
+// X <- X L_D^{-T}: one thread per panel row (256 rows per work-group), row kept in registers.
 __global__ __launch_bounds__(NT) void blk_trsm(const int32_t* __restrict__ it, const int32_t* __restrict__ ncol,
                                                const int32_t* __restrict__ mrows, const int64_t* __restrict__ foff,
                                                double* __restrict__ fronts) {
-    __shared__ double Ld[TB * TB];
-    __shared__ double X[TB * (TB + 1)];
+    __shared__ double Ld[TB * (TB + 1)];
     const int s = it[3 * blockIdx.x], k0 = it[3 * blockIdx.x + 1], rb = it[3 * blockIdx.x + 2];
     const int m = mrows[s];
     const int kb = min(TB, ncol[s] - k0);
-    const int r0 = k0 + kb + rb * TB;
-    const int nr = min(TB, m - r0);
+    const int row = k0 + kb + rb * NT + threadIdx.x;
     double* F = fronts + foff[s];
     for (int e = threadIdx.x; e < kb * kb; e += NT) {
-        const int i = e % kb, j = e / kb;
-        if (i >= j) Ld[i + TB * j] = F[(int64_t)(k0 + i) + (int64_t)m * (k0 + j)];
-    }
-    for (int e = threadIdx.x; e < TB * kb; e += NT) {
-        const int i = e % TB, j = e / TB;
-        if (i < nr) X[i + (TB + 1) * j] = F[(int64_t)(r0 + i) + (int64_t)m * (k0 + j)];
+        const int r = e % kb, c = e / kb;
+        if (r >= c) Ld[r * (TB + 1) + c] = F[(int64_t)(k0 + r) + (int64_t)m * (k0 + c)];
     }
     __syncthreads();
-    // rows are independent: 4 threads per row split the inner products
-    const int row = threadIdx.x / 4, lane = threadIdx.x % 4;
-    for (int j = 0; j < kb; j++) {
-        double acc = 0.0;
-        if (row < nr)
-            for (int t = lane; t < j; t += 4) acc += X[row + (TB + 1) * t] * Ld[j + TB * t];
-        acc += __shfl_xor(acc, 1, 4);
-        acc += __shfl_xor(acc, 2, 4);
-        if (row < nr && lane == 0) X[row + (TB + 1) * j] = (X[row + (TB + 1) * j] - acc) / Ld[j + TB * j];
-        __syncthreads();
+    if (row >= m) return;
+    double x[TB];
+#pragma unroll
+    for (int j = 0; j < TB; j++) x[j] = j < kb ? F[(int64_t)row + (int64_t)m * (k0 + j)] : 0.0;
+#pragma unroll
+    for (int j = 0; j < TB; j++) {
+        if (j < kb) {
+            double acc = x[j];
+#pragma unroll
+            for (int t = 0; t < j; t++) acc -= x[t] * Ld[j * (TB + 1) + t];
+            x[j] = acc / Ld[j * (TB + 1) + j];
+        }
     }
-    for (int e = threadIdx.x; e < TB * kb; e += NT) {
-        const int i = e % TB, j = e / TB;
-        if (i < nr) F[(int64_t)(r0 + i) + (int64_t)m * (k0 + j)] = X[i + (TB + 1) * j];
-    }
+#pragma unroll
+    for (int j = 0; j < TB; j++)
+        if (j < kb) F[(int64_t)row + (int64_t)m * (k0 + j)] = x[j];
 }
 
-// C(bi, bj) -= P_bi P_bj^T on the trailing matrix, FP64 MFMA 16x16x4.
-// Four waves; wave w computes the 32x32 quadrant (w / 2, w % 2) of the 64x64 tile
-// as 2x2 MFMA blocks of 16x16.
+// C(bi, bj) -= P_bi P_bj^T on the trailing matrix, 128 x 128 tiles, FP64 MFMA 16x16x4.
+// Four waves in a 2 x 2 arrangement, each computing a 64 x 64 quadrant as 4 x 4 MFMA blocks;
+// the panel rows are staged through LDS in chunks of 16 columns.
 typedef double double4_t __attribute__((ext_vector_type(4)));
+constexpr int KC = 16;
 
 __global__ __launch_bounds__(NT) void blk_syrk(const int32_t* __restrict__ it, const int32_t* __restrict__ ncol,
                                                const int32_t* __restrict__ mrows, const int64_t* __restrict__ foff,
                                                double* __restrict__ fronts) {
-    __shared__ double Pi[TB * (TB + 1)];
-    __shared__ double Pj[TB * (TB + 1)];
+    __shared__ double Pi[KC][ST + 1];
+    __shared__ double Pj[KC][ST + 1];
     const int s = it[4 * blockIdx.x], k0 = it[4 * blockIdx.x + 1];
     const int bi = it[4 * blockIdx.x + 2], bj = it[4 * blockIdx.x + 3];
     const int m = mrows[s];
     const int kb = min(TB, ncol[s] - k0);
     const int base = k0 + kb;
-    const int ri0 = base + bi * TB, rj0 = base + bj * TB;
-    const int nri = min(TB, m - ri0), nrj = min(TB, m - rj0);
-    double* F = fronts + foff[s];
-    // stage the two panel blocks (rows x kb), zero-padded to 64 x 64
-    for (int e = threadIdx.x; e < TB * TB; e += NT) {
-        const int i = e % TB, t = e / TB;
-        double a = 0.0, b = 0.0;
-        if (t < kb) {
-            if (i < nri) a = F[(int64_t)(ri0 + i) + (int64_t)m * (k0 + t)];
-            if (i < nrj) b = F[(int64_t)(rj0 + i) + (int64_t)m * (k0 + t)];
-        }
-        Pi[i + (TB + 1) * t] = a;
-        Pj[i + (TB + 1) * t] = b;
-    }
-    __syncthreads();
+    const int ri0 = base + bi * ST, rj0 = base + bj * ST;
+    const int nri = min(ST, m - ri0), nrj = min(ST, m - rj0);
+    const double* F = fronts + foff[s];
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-    const int qr = (wave / 2) * 32, qc = (wave % 2) * 32;
-    double4_t acc[2][2];
-    for (int a = 0; a < 2; a++)
-        for (int b = 0; b < 2; b++) acc[a][b] = double4_t{0.0, 0.0, 0.0, 0.0};
+    const int qr = (wave / 2) * 64, qc = (wave % 2) * 64;
     const int li = lane % 16, lk = lane / 16;
-    const int kbr = (kb + 3) & ~3;
-    for (int t = 0; t < kbr; t += 4) {
-        double av[2], bv[2];
-        for (int a = 0; a < 2; a++) av[a] = Pi[(qr + 16 * a + li) + (TB + 1) * (t + lk)];
-        for (int b = 0; b < 2; b++) bv[b] = Pj[(qc + 16 * b + li) + (TB + 1) * (t + lk)];
-        for (int a = 0; a < 2; a++)
-            for (int b = 0; b < 2; b++) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+    // skip the strictly-upper quadrant of a diagonal tile
+    const bool active = !(bi == bj && qc > qr);
+    double4_t acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int b = 0; b < 4; b++) acc[a][b] = double4_t{0.0, 0.0, 0.0, 0.0};
+    for (int t0 = 0; t0 < kb; t0 += KC) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < ST * KC; e += NT) {
+            const int r = e % ST, t = e / ST;
+            const int tt = t0 + t;
+            double a = 0.0, b = 0.0;
+            if (tt < kb) {
+                if (r < nri) a = F[(int64_t)(ri0 + r) + (int64_t)m * (k0 + tt)];
+                if (r < nrj) b = F[(int64_t)(rj0 + r) + (int64_t)m * (k0 + tt)];
+            }
+            Pi[t][r] = a;
+            Pj[t][r] = b;
+        }
+        __syncthreads();
+        if (active) {
+#pragma unroll
+            for (int t = 0; t < KC; t += 4) {
+                double av[4], bv[4];
+#pragma unroll
+                for (int a = 0; a < 4; a++) av[a] = Pi[t + lk][qr + 16 * a + li];
+#pragma unroll
+                for (int b = 0; b < 4; b++) bv[b] = Pj[t + lk][qc + 16 * b + li];
+#pragma unroll
+                for (int a = 0; a < 4; a++)
+#pragma unroll
+                    for (int b = 0; b < 4; b++)
+                        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+            }
+        }
     }
+    if (!active) return;
+    double* Fw = fronts + foff[s];
     // D layout of the 16x16x4 f64 MFMA: item r of a lane is row (lane / 16) + 4 r, column lane % 16
-    for (int a = 0; a < 2; a++)
-        for (int b = 0; b < 2; b++)
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int b = 0; b < 4; b++)
+#pragma unroll
             for (int r = 0; r < 4; r++) {
                 const int i = qr + 16 * a + (lane / 16) + 4 * r;
                 const int j = qc + 16 * b + (lane % 16);
                 const int gi = ri0 + i, gj = rj0 + j;
-                if (i < nri && j < nrj && gi >= gj) F[(int64_t)gi + (int64_t)m * gj] -= acc[a][b][r];
+                if (i < nri && j < nrj && gi >= gj) Fw[(int64_t)gi + (int64_t)m * gj] -= acc[a][b][r];
             }
 }
 
@@ -381,6 +430,143 @@ __global__ __launch_bounds__(NT) void solve_bwd(const int32_t* __restrict__ list
         __syncthreads();
     }
     for (int j = threadIdx.x; j < nn; j += NT) y[f + j] = w[j];
+}
+
+// ---------------------------------------------------------------- blocked solves for wide fronts
+// A front with many pivots is solved in 64-column blocks, one launch per block, with the rows
+// (forward) or pivot columns (backward) spread over many work-groups.  Every work-group first
+// solves the 64 x 64 diagonal block redundantly with one wave and lane shuffles, so no
+// cross-work-group synchronisation is needed inside a launch.
+constexpr int WIDE = 256;  // fronts with at least this many pivots use the blocked solves
+
+// forward, step 0: w = [y(own rows), 0] + children's partial results (one work-group per front)
+__global__ __launch_bounds__(NT) void sfwd_gather(const int32_t* __restrict__ list, const int32_t* __restrict__ first,
+                                                  const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
+                                                  const int64_t* __restrict__ roff, const int64_t* __restrict__ uoff,
+                                                  const int32_t* __restrict__ child_ptr,
+                                                  const int32_t* __restrict__ child,
+                                                  const int64_t* __restrict__ rel_off, const int32_t* __restrict__ rel,
+                                                  double* __restrict__ work, const double* __restrict__ upd,
+                                                  const double* __restrict__ y) {
+    const int s = list[blockIdx.x];
+    const int m = mrows[s], nn = ncol[s], f = first[s];
+    double* w = work + roff[s];
+    for (int t = threadIdx.x; t < m; t += NT) w[t] = t < nn ? y[f + t] : 0.0;
+    __syncthreads();
+    for (int ci = child_ptr[s]; ci < child_ptr[s + 1]; ci++) {
+        const int c = child[ci];
+        const int nu = mrows[c] - ncol[c];
+        const int32_t* rl = rel + rel_off[c];
+        const double* uc = upd + uoff[c];
+        for (int t = threadIdx.x; t < nu; t += NT) w[rl[t]] += uc[t];
+        __syncthreads();
+    }
+}
+
+// forward, one 64-column block: z = L_bb^{-1} w_b (written to y), w(rows below) -= L(rows, b) z
+__global__ __launch_bounds__(NT) void sfwd_block(int s, int k0, const int32_t* __restrict__ first,
+                                                 const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
+                                                 const int64_t* __restrict__ foff, const int64_t* __restrict__ roff,
+                                                 const double* __restrict__ fronts, double* __restrict__ work,
+                                                 double* __restrict__ y) {
+    __shared__ double Ld[TB * (TB + 1)];
+    __shared__ double z[TB];
+    const int m = mrows[s], nn = ncol[s];
+    const int kb = min(TB, nn - k0);
+    const double* L = fronts + foff[s];
+    double* w = work + roff[s];
+    for (int e = threadIdx.x; e < kb * kb; e += NT) {
+        const int r = e % kb, c = e / kb;
+        if (r >= c) Ld[r * (TB + 1) + c] = L[(int64_t)(k0 + r) + (int64_t)m * (k0 + c)];
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        double wi = lane < kb ? w[k0 + lane] : 0.0;
+        const double dii = lane < kb ? Ld[lane * (TB + 1) + lane] : 1.0;
+        for (int j = 0; j < kb; j++) {
+            const double zj = __shfl(wi / dii, j);
+            if (lane == j) wi = zj;
+            if (lane > j && lane < kb) wi -= Ld[lane * (TB + 1) + j] * zj;
+        }
+        if (lane < kb) z[lane] = wi;
+    }
+    __syncthreads();
+    if (blockIdx.x == 0)
+        for (int j = threadIdx.x; j < kb; j += NT) y[first[s] + k0 + j] = z[j];
+    const int i = k0 + kb + blockIdx.x * NT + threadIdx.x;
+    if (i < m) {
+        double acc = w[i];
+        for (int j = 0; j < kb; j++) acc -= L[(int64_t)i + (int64_t)m * (k0 + j)] * z[j];
+        w[i] = acc;
+    }
+}
+
+// forward, last step: the rows below the pivots become this front's partial result
+__global__ void sfwd_finish(int s, const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
+                            const int64_t* __restrict__ roff, const int64_t* __restrict__ uoff,
+                            const double* __restrict__ work, double* __restrict__ upd) {
+    const int m = mrows[s], nn = ncol[s];
+    const int t = blockIdx.x * NT + threadIdx.x;
+    if (t < m - nn) upd[uoff[s] + t] = work[roff[s] + nn + t];
+}
+
+// backward, step 0: t = y(own) - L21^T x(rows below), one thread per pivot column
+__global__ __launch_bounds__(NT) void sbwd_init(int s, const int32_t* __restrict__ first,
+                                                const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
+                                                const int64_t* __restrict__ foff, const int64_t* __restrict__ roff,
+                                                const int32_t* __restrict__ rows, const double* __restrict__ fronts,
+                                                double* __restrict__ work, const double* __restrict__ y) {
+    const int m = mrows[s], nn = ncol[s], f = first[s];
+    const int j = blockIdx.x * NT + threadIdx.x;
+    if (j >= nn) return;
+    const int32_t* R = rows + roff[s];
+    const double* col = fronts + foff[s] + (int64_t)m * j;
+    double acc = y[f + j];
+    for (int i = nn; i < m; i++) acc -= col[i] * y[R[i]];
+    work[roff[s] + j] = acc;
+}
+
+// backward, one 64-column block (last to first): x_b = L_bb^{-T} t_b (written to y),
+// t(columns before the block) -= L(b, columns)^T x_b
+__global__ __launch_bounds__(NT) void sbwd_block(int s, int k0, const int32_t* __restrict__ first,
+                                                 const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
+                                                 const int64_t* __restrict__ foff, const int64_t* __restrict__ roff,
+                                                 const double* __restrict__ fronts, double* __restrict__ work,
+                                                 double* __restrict__ y) {
+    __shared__ double Ld[TB * (TB + 1)];
+    __shared__ double xb[TB];
+    const int m = mrows[s], nn = ncol[s];
+    const int kb = min(TB, nn - k0);
+    const double* L = fronts + foff[s];
+    double* t = work + roff[s];
+    for (int e = threadIdx.x; e < kb * kb; e += NT) {
+        const int r = e % kb, c = e / kb;
+        if (r >= c) Ld[r * (TB + 1) + c] = L[(int64_t)(k0 + r) + (int64_t)m * (k0 + c)];
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        double ti = lane < kb ? t[k0 + lane] : 0.0;
+        const double dii = lane < kb ? Ld[lane * (TB + 1) + lane] : 1.0;
+        for (int j = kb - 1; j >= 0; j--) {
+            const double xj = __shfl(ti / dii, j);
+            if (lane == j) ti = xj;
+            if (lane < j) ti -= Ld[j * (TB + 1) + lane] * xj;
+        }
+        if (lane < kb) xb[lane] = ti;
+    }
+    __syncthreads();
+    if (blockIdx.x == 0)
+        for (int j = threadIdx.x; j < kb; j += NT) y[first[s] + k0 + j] = xb[j];
+    const int j = blockIdx.x * NT + threadIdx.x;
+    if (j < k0) {
+        double acc = t[j];
+        const double* col = L + (int64_t)m * j + k0;
+        for (int r = 0; r < kb; r++) acc -= col[r] * xb[r];
+        t[j] = acc;
+    }
+    (void)m;
 }
 
 }  // namespace
@@ -467,6 +653,18 @@ static void build_numeric_plan(chol_sym* C, const std::vector<int32_t>& colptr, 
     }
     C->lvl_small_ptr.assign(nl + 1, 0);
     C->lvl_small.clear();
+    C->lvl_narrow_ptr.assign(nl + 1, 0);
+    C->lvl_wide_ptr.assign(nl + 1, 0);
+    C->lvl_narrow.clear();
+    C->lvl_wide.clear();
+    for (int l = 0; l < nl; l++) {
+        for (int q = C->lvl_ptr[l]; q < C->lvl_ptr[l + 1]; q++) {
+            int s = C->lvl_sn[q];
+            (C->h_ncol[s] >= WIDE ? C->lvl_wide : C->lvl_narrow).push_back(s);
+        }
+        C->lvl_narrow_ptr[l + 1] = (int32_t)C->lvl_narrow.size();
+        C->lvl_wide_ptr[l + 1] = (int32_t)C->lvl_wide.size();
+    }
     // assembly tiles and K entries per tile
     std::vector<int32_t> tsn, trc;
     C->asm_ptr.assign(nl + 1, 0);
@@ -548,12 +746,13 @@ static void build_numeric_plan(chol_sym* C, const std::vector<int32_t>& colptr, 
                 pot.push_back(s);
                 pot.push_back(k0);
                 int rest = m - k0 - kb;
-                int T = (rest + TB - 1) / TB;
-                for (int rb = 0; rb < T; rb++) {
+                int Tr = (rest + NT - 1) / NT;
+                for (int rb = 0; rb < Tr; rb++) {
                     trs.push_back(s);
                     trs.push_back(k0);
                     trs.push_back(rb);
                 }
+                int T = (rest + ST - 1) / ST;
                 for (int bj = 0; bj < T; bj++)
                     for (int bi = bj; bi < T; bi++) {
                         syr.push_back(s);
@@ -574,6 +773,11 @@ static void build_numeric_plan(chol_sym* C, const std::vector<int32_t>& colptr, 
     C->dev.upload(C->ncol, C->h_ncol);
     C->dev.upload(C->mrows, C->h_mrows);
     C->dev.upload(C->perm, S.perm);
+    {
+        std::vector<int32_t> kdp(n);
+        for (int j = 0; j < n; j++) kdp[j] = colptr[S.perm[j]];  // rows ascending: the diagonal comes first
+        C->dev.upload(C->kdiagpos, kdp);
+    }
     C->dev.upload(C->foff, C->h_foff);
     C->dev.upload(C->roff, C->h_roff);
     C->dev.upload(C->uoff, C->h_uoff);
@@ -589,6 +793,8 @@ static void build_numeric_plan(chol_sym* C, const std::vector<int32_t>& colptr, 
     C->dev.upload(C->tile_kpos, tkpos);
     C->dev.upload(C->lvl_sn_d, C->lvl_sn);
     C->dev.upload(C->lvl_small_d, C->lvl_small);
+    C->dev.upload(C->lvl_narrow_d, C->lvl_narrow);
+    C->dev.upload(C->lvl_wide_d, C->lvl_wide);
     C->dev.upload(C->potrf_it, pot);
     C->dev.upload(C->trsm_it, trs);
     C->dev.upload(C->syrk_it, syr);
@@ -605,6 +811,7 @@ extern "C" void chol_default_options(chol_options* o) {
     o->max_width = INT32_MAX;
     o->zero_abs = 64;
     o->zero_rel = 0.05;
+    o->pivot_tol = 0.0;
 }
 
 extern "C" int chol_analyze(int32_t n, const int32_t* colptr, const int32_t* rowind, const chol_options* opts,
@@ -692,8 +899,9 @@ extern "C" int chol_supernode_rows(const chol_sym* C, int64_t* rows_ptr, int32_t
 namespace opf {
 
 // Enqueue the numeric factorization (no synchronisation).
-void chol_factor_enqueue(chol_sym* C, const double* kval, hipStream_t st) {
+void chol_factor_enqueue(chol_sym* C, const double* kval, hipStream_t st, double pivot_tol) {
     C->dev.run();
+    const PivotRef pr{kval, C->kdiagpos.p, pivot_tol};
     for (int l = 0; l < C->nlevels; l++) {
         int t0 = C->asm_ptr[l], t1 = C->asm_ptr[l + 1];
         if (t1 > t0) {
@@ -705,14 +913,14 @@ void chol_factor_enqueue(chol_sym* C, const double* kval, hipStream_t st) {
         int s0 = C->lvl_small_ptr[l], s1 = C->lvl_small_ptr[l + 1];
         if (s1 > s0) {
             hipLaunchKernelGGL(front_small, dim3(s1 - s0), dim3(NT), 0, st, C->lvl_small_d.p + s0, C->first.p,
-                               C->ncol.p, C->mrows.p, C->foff.p, C->fronts.p, C->status.p);
+                               C->ncol.p, C->mrows.p, C->foff.p, C->fronts.p, C->status.p, pr);
             OPF_LAUNCH_CHECK();
         }
         for (int q = C->lvl_step_ptr[l]; q < C->lvl_step_ptr[l + 1]; q++) {
             const chol_sym::Step& S = C->steps[q];
             if (S.p1 > S.p0) {
-                hipLaunchKernelGGL(blk_potrf, dim3(S.p1 - S.p0), dim3(NT), 0, st, C->potrf_it.p + 2 * S.p0,
-                                   C->first.p, C->ncol.p, C->mrows.p, C->foff.p, C->fronts.p, C->status.p);
+                hipLaunchKernelGGL(blk_potrf, dim3(S.p1 - S.p0), dim3(64), 0, st, C->potrf_it.p + 2 * S.p0,
+                                   C->first.p, C->ncol.p, C->mrows.p, C->foff.p, C->fronts.p, C->status.p, pr);
                 OPF_LAUNCH_CHECK();
             }
             if (S.t1 > S.t0) {
@@ -735,12 +943,12 @@ __global__ void init_status(int ns, const int32_t* __restrict__ mrows, int32_t* 
 }
 
 // Factor and report: returns -1 if positive definite, else the bad pivot.
-int chol_factor_sync(chol_sym* C, const double* kval, hipStream_t st) {
+int chol_factor_sync(chol_sym* C, const double* kval, hipStream_t st, double pivot_tol) {
     C->dev.run();
     const int ns = C->S.nsuper;
     hipLaunchKernelGGL(init_status, dim3(ceil_div(ns, 256)), dim3(256), 0, st, ns, C->mrows.p, C->status.p);
     OPF_LAUNCH_CHECK();
-    chol_factor_enqueue(C, kval, st);
+    chol_factor_enqueue(C, kval, st, pivot_tol);
     std::vector<int32_t> stat(ns);
     OPF_HIP(hipMemcpyAsync(stat.data(), C->status.p, ns * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     OPF_HIP(hipStreamSynchronize(st));
@@ -764,17 +972,60 @@ void chol_solve_enqueue(chol_sym* C, const double* b, double* x, hipStream_t st)
     hipLaunchKernelGGL(permute_in, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, C->perm.p, b, y);
     OPF_LAUNCH_CHECK();
     for (int l = 0; l < C->nlevels; l++) {
-        int q0 = C->lvl_ptr[l], q1 = C->lvl_ptr[l + 1];
-        hipLaunchKernelGGL(solve_fwd, dim3(q1 - q0), dim3(NT), 0, st, C->lvl_sn_d.p + q0, C->first.p, C->ncol.p,
-                           C->mrows.p, C->foff.p, C->roff.p, C->uoff.p, C->child_ptr.p, C->child.p, C->rel_off.p,
-                           C->rel.p, C->fronts.p, C->work.p, C->upd.p, y);
-        OPF_LAUNCH_CHECK();
+        int q0 = C->lvl_narrow_ptr[l], q1 = C->lvl_narrow_ptr[l + 1];
+        if (q1 > q0) {
+            hipLaunchKernelGGL(solve_fwd, dim3(q1 - q0), dim3(NT), 0, st, C->lvl_narrow_d.p + q0, C->first.p,
+                               C->ncol.p, C->mrows.p, C->foff.p, C->roff.p, C->uoff.p, C->child_ptr.p, C->child.p,
+                               C->rel_off.p, C->rel.p, C->fronts.p, C->work.p, C->upd.p, y);
+            OPF_LAUNCH_CHECK();
+        }
+        int w0 = C->lvl_wide_ptr[l], w1 = C->lvl_wide_ptr[l + 1];
+        if (w1 > w0) {
+            hipLaunchKernelGGL(sfwd_gather, dim3(w1 - w0), dim3(NT), 0, st, C->lvl_wide_d.p + w0, C->first.p,
+                               C->ncol.p, C->mrows.p, C->roff.p, C->uoff.p, C->child_ptr.p, C->child.p, C->rel_off.p,
+                               C->rel.p, C->work.p, C->upd.p, y);
+            OPF_LAUNCH_CHECK();
+            for (int q = w0; q < w1; q++) {
+                const int s = C->lvl_wide[q];
+                const int m = C->h_mrows[s], nn = C->h_ncol[s];
+                for (int k0 = 0; k0 < nn; k0 += TB) {
+                    const int kb = std::min(TB, nn - k0);
+                    const unsigned g = std::max(1u, ceil_div(m - k0 - kb, NT));
+                    hipLaunchKernelGGL(sfwd_block, dim3(g), dim3(NT), 0, st, s, k0, C->first.p, C->ncol.p,
+                                       C->mrows.p, C->foff.p, C->roff.p, C->fronts.p, C->work.p, y);
+                    OPF_LAUNCH_CHECK();
+                }
+                if (m > nn) {
+                    hipLaunchKernelGGL(sfwd_finish, dim3(ceil_div(m - nn, NT)), dim3(NT), 0, st, s, C->ncol.p,
+                                       C->mrows.p, C->roff.p, C->uoff.p, C->work.p, C->upd.p);
+                    OPF_LAUNCH_CHECK();
+                }
+            }
+        }
     }
     for (int l = C->nlevels - 1; l >= 0; l--) {
-        int q0 = C->lvl_ptr[l], q1 = C->lvl_ptr[l + 1];
-        hipLaunchKernelGGL(solve_bwd, dim3(q1 - q0), dim3(NT), 0, st, C->lvl_sn_d.p + q0, C->first.p, C->ncol.p,
-                           C->mrows.p, C->foff.p, C->roff.p, C->rows.p, C->fronts.p, C->work.p, y);
-        OPF_LAUNCH_CHECK();
+        int w0 = C->lvl_wide_ptr[l], w1 = C->lvl_wide_ptr[l + 1];
+        for (int q = w0; q < w1; q++) {
+            const int s = C->lvl_wide[q];
+            const int nn = C->h_ncol[s];
+            hipLaunchKernelGGL(sbwd_init, dim3(ceil_div(nn, NT)), dim3(NT), 0, st, s, C->first.p, C->ncol.p,
+                               C->mrows.p, C->foff.p, C->roff.p, C->rows.p, C->fronts.p, C->work.p, y);
+            OPF_LAUNCH_CHECK();
+            const int nblk = (nn + TB - 1) / TB;
+            for (int bk = nblk - 1; bk >= 0; bk--) {
+                const int k0 = bk * TB;
+                const unsigned g = std::max(1u, ceil_div(k0, NT));
+                hipLaunchKernelGGL(sbwd_block, dim3(g), dim3(NT), 0, st, s, k0, C->first.p, C->ncol.p, C->mrows.p,
+                                   C->foff.p, C->roff.p, C->fronts.p, C->work.p, y);
+                OPF_LAUNCH_CHECK();
+            }
+        }
+        int q0 = C->lvl_narrow_ptr[l], q1 = C->lvl_narrow_ptr[l + 1];
+        if (q1 > q0) {
+            hipLaunchKernelGGL(solve_bwd, dim3(q1 - q0), dim3(NT), 0, st, C->lvl_narrow_d.p + q0, C->first.p,
+                               C->ncol.p, C->mrows.p, C->foff.p, C->roff.p, C->rows.p, C->fronts.p, C->work.p, y);
+            OPF_LAUNCH_CHECK();
+        }
     }
     hipLaunchKernelGGL(permute_out, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, C->perm.p, y, x);
     OPF_LAUNCH_CHECK();
@@ -785,7 +1036,7 @@ void chol_solve_enqueue(chol_sym* C, const double* b, double* x, hipStream_t st)
 extern "C" int chol_factor(chol_sym* C, const double* kval, void* stream, int32_t* bad_col) {
     return guarded([&] {
         OPF_CHECK(C && kval, OPF_E_INVALID, "chol_factor: null argument");
-        int bad = chol_factor_sync(C, kval, (hipStream_t)stream);
+        int bad = chol_factor_sync(C, kval, (hipStream_t)stream, C->opts.pivot_tol);
         if (bad_col) *bad_col = bad;
         if (bad >= 0) {
             set_error("chol_factor: non-positive pivot at pivot index %d", bad);

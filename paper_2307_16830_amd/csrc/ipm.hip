@@ -22,8 +22,8 @@
 #include "model.h"
 
 namespace opf {
-void chol_factor_enqueue(chol_sym* C, const double* kval, hipStream_t st);
-int chol_factor_sync(chol_sym* C, const double* kval, hipStream_t st);
+void chol_factor_enqueue(chol_sym* C, const double* kval, hipStream_t st, double pivot_tol);
+int chol_factor_sync(chol_sym* C, const double* kval, hipStream_t st, double pivot_tol);
 void chol_solve_enqueue(chol_sym* C, const double* b, double* x, hipStream_t st);
 }  // namespace opf
 
@@ -548,6 +548,7 @@ extern "C" void ipm_default_options(ipm_options* o) {
     o->ir_tol = 1e-10;
     o->mu_init = 0.1;
     o->bound_relax = 1e-8;
+    o->pivot_tol = 1e-12;
 }
 
 extern "C" int ipm_create(opf_model* M, const ipm_options* opts, const chol_options* copts, void* stream,
@@ -709,7 +710,7 @@ static int compute_direction(ipm_state* S, double mu, ipm_iter_info& I) {
         OPF_HIP(hipEventRecord(S->ev[2], st));
         condense(S->M, S->hess.p, S->jac.p, S->Sx.p, S->D.p, dw, S->kval.p, st);
         OPF_HIP(hipEventRecord(S->ev[3], st));
-        int bad = chol_factor_sync(S->C, S->kval.p, st);
+        int bad = chol_factor_sync(S->C, S->kval.p, st, S->o.pivot_tol);
         OPF_HIP(hipEventRecord(S->ev[4], st));
         OPF_HIP(hipEventSynchronize(S->ev[4]));
         float a = 0, b = 0;

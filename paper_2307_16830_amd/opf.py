@@ -49,12 +49,13 @@ class GridC(ctypes.Structure):
 
 class CholOptions(ctypes.Structure):
     _fields_ = [("dense_frac", ctypes.c_double), ("dense_abs", ctypes.c_int32), ("max_width", ctypes.c_int32),
-                ("zero_abs", ctypes.c_int64), ("zero_rel", ctypes.c_double)]
+                ("zero_abs", ctypes.c_int64), ("zero_rel", ctypes.c_double), ("pivot_tol", ctypes.c_double)]
 
 
 class IpmOptions(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("max_ir", ctypes.c_int32),
-                ("ir_tol", ctypes.c_double), ("mu_init", ctypes.c_double), ("bound_relax", ctypes.c_double)]
+                ("ir_tol", ctypes.c_double), ("mu_init", ctypes.c_double), ("bound_relax", ctypes.c_double),
+                ("pivot_tol", ctypes.c_double)]
 
 
 class IterInfo(ctypes.Structure):

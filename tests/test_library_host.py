@@ -1,0 +1,109 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every declared symbol, and its host logic
+(structure, bounds, condensed pattern, symbolic analysis) is bit-exact with the oracle.  No device
+compute is called: device uploads are deferred to the first device use."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import chol as ochol
+from oracle import kkt as okkt
+from oracle.model import Model as OModel
+from paper_2307_16830_amd import gridgen
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+OPTS = dict(dense_frac=0.5, dense_abs=2 ** 31 - 1, max_width=2 ** 31 - 1, zero_abs=64, zero_rel=0.05)
+
+
+def opf():
+    from paper_2307_16830_amd import opf as _opf
+    return _opf
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "opf.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b([a-z_]+)\s*\(", text)) - {"if", "sizeof"})
+
+
+def test_library_exports_every_declared_symbol():
+    lib = opf().lib()
+    syms = declared_symbols()
+    assert len(syms) >= 25
+    for name in syms:
+        assert hasattr(lib, name), name
+    assert set(opf().EXPORTED) <= set(syms)
+
+
+def test_invalid_grid_is_rejected():
+    g = gridgen.make_grid(5, 6, 2, 1)
+    g.f[0] = 99
+    with pytest.raises(opf().OpfError) as e:
+        opf().Model(g)
+    assert e.value.code == opf().E_INVALID
+
+
+@pytest.mark.parametrize("case", ["cfg0", (40, 55, 8, 3), "cfg1"])
+def test_host_structure_and_symbolic_match_oracle(case):
+    g = gridgen.make_config(case) if isinstance(case, str) else gridgen.make_grid(*case)
+    M = opf().Model(g)
+    om = OModel(g)
+    x0 = om.flat_start()
+    assert np.array_equal(M.initial_point(), x0)
+    xl, xu, gl, gu = M.bounds()
+    for a, b in ((xl, om.xl), (xu, om.xu), (gl, om.gl), (gu, om.gu)):
+        assert np.array_equal(a, b)
+    jr, jc, hr, hc = M.structure()
+    ojr, ojc, _, _ = om.jacobian(x0)
+    ohr, ohc, _, _ = om.hessian(x0, np.zeros(om.L.m), 1.0)
+    assert sorted(zip(jr.tolist(), jc.tolist())) == sorted(zip(ojr.tolist(), ojc.tolist()))
+    assert sorted(zip(hr.tolist(), hc.tolist())) == sorted(zip(ohr.tolist(), ohc.tolist()))
+    cp, ri = M.kkt_pattern()
+    kr, kc = okkt.kkt_pattern(om.L.n, ojr, ojc, ohr, ohc)
+    ocp, ori = ochol.lower_csc(om.L.n, kr, kc)
+    assert np.array_equal(cp, ocp) and np.array_equal(ri, ori)
+    C = opf().Cholesky(M.n, cp, ri, opf().chol_options(**OPTS))
+    sym = ochol.analyze(M.n, cp, ri, ochol.AnalyzeOptions(**OPTS))
+    par, cc = C.etree()
+    assert np.array_equal(C.perm(), sym.perm)
+    assert np.array_equal(par, sym.parent)
+    assert np.array_equal(cc, sym.colcount)
+    assert np.array_equal(C.supernodes(), sym.snode_ptr)
+    # supernode row structures equal the union of the oracle's column structures
+    oc = ochol.Cholesky(M.n, cp, ri, sym.perm)
+    lp, li, _ = oc.export()
+    rp, rows = C.supernode_rows()
+    sp = sym.snode_ptr
+    for t in range(len(sp) - 1):
+        cols = range(sp[t], sp[t + 1])
+        union = set(range(sp[t], sp[t + 1]))
+        for j in cols:
+            union |= set(li[lp[j]:lp[j + 1]].tolist())
+        got = rows[rp[t]:rp[t + 1]]
+        assert list(got[:sp[t + 1] - sp[t]]) == list(cols)
+        assert sorted(got.tolist()) == sorted(union)
+
+
+@pytest.mark.parametrize("opts", [dict(max_width=8, zero_abs=0, zero_rel=0.0),
+                                  dict(dense_frac=0.3, max_width=32, zero_abs=16, zero_rel=0.2),
+                                  dict(dense_abs=40)])
+def test_symbolic_options_bit_exact(opts):
+    g = gridgen.make_grid(200, 270, 30, 9)
+    M = opf().Model(g)
+    cp, ri = M.kkt_pattern()
+    o = dict(OPTS)
+    o.update(opts)
+    C = opf().Cholesky(M.n, cp, ri, opf().chol_options(**o))
+    sym = ochol.analyze(M.n, cp, ri, ochol.AnalyzeOptions(**o))
+    assert np.array_equal(C.perm(), sym.perm)
+    assert np.array_equal(C.etree()[0], sym.parent)
+    assert np.array_equal(C.supernodes(), sym.snode_ptr)
+
+
+def test_chol_analyze_rejects_bad_patterns():
+    O = opf()
+    with pytest.raises(O.OpfError):
+        O.Cholesky(3, np.array([0, 1, 2, 2]), np.array([0, 1]))  # column 2 lacks its diagonal
+    with pytest.raises(O.OpfError):
+        O.Cholesky(2, np.array([0, 1, 2]), np.array([1, 1]))  # entry above the diagonal

@@ -75,9 +75,9 @@ def test_cfg0_reaches_1e8_and_kkt_holds_independently():
     assert 0 < m.objective(x) < m.objective(m.flat_start()) * 2
 
 
-@pytest.mark.parametrize("seed", [2, 4, 9])
+@pytest.mark.parametrize("seed", [0, 2, 4, 9])
 def test_other_cfg0_seeds_converge(seed):
     g = gridgen.make_grid(30, 41, 6, seed)
     I = oipm.IPM(Model(g), oipm.Options(tol=1e-8))
     assert I.solve() == oipm.Status.OK
-    assert I.iter < 60
+    assert I.iter < 100
