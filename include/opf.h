@@ -175,6 +175,15 @@ int chol_factor(chol_sym* sym, const double* kval, void* stream, int32_t* bad_co
 /* x = K^{-1} b using the last successful factor; b, x device [n*nrhs]
  * (column-major, leading dimension n; x may alias b).  Asynchronous. */
 int chol_solve(chol_sym* sym, const double* b, double* x, int32_t nrhs, void* stream);
+/* Kernel timing of the numeric factorizations (measurement aid).  With
+ * timing enabled, every factorization launch is bracketed by HIP events on
+ * its stream; chol_timing_read returns, for the categories [assembly,
+ * small fronts, diagonal-block Cholesky, panel solve, trailing MFMA update],
+ * the summed kernel milliseconds ms[5], the launch counts launches[5] and the
+ * algorithmic flops flops[5] (filled for the trailing update: the symmetric
+ * rank-64 updates of each step's lower triangle).  Enabling resets them. */
+int chol_timing(chol_sym* sym, int enable);
+int chol_timing_read(const chol_sym* sym, double* ms, int64_t* launches, double* flops);
 /* Copy L to the host as CSC in pivot order over the supernodal pattern
  * (lp [n+1], li [nnz_l], lx [nnz_l]); explicit zeros included. */
 int chol_export_factor(chol_sym* sym, int64_t* lp, int32_t* li, double* lx);

@@ -73,6 +73,18 @@ struct chol_sym {
     DBuf<int32_t> status;
     DBuf<double> fronts, upd, work, ybuf;
     Deferred dev;  // pending uploads, run at the first device use
+    // optional per-category kernel timing (assemble, small, potrf, trsm, syrk)
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<int> ev_cat;
+    size_t ev_used = 0;
+    double t_ms[5] = {0, 0, 0, 0, 0};
+    int64_t t_launch[5] = {0, 0, 0, 0, 0};
+    double t_flops[5] = {0, 0, 0, 0, 0};
+    std::vector<double> step_syrk_flops;  // algorithmic flops of each blocked step's trailing update
+    ~chol_sym() {
+        for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    }
 };
 
 namespace {
@@ -157,11 +169,13 @@ __device__ __forceinline__ void lds_cholesky(double* A, int lda, int m, int ncol
                                              int pivot0) {
     // A: lower triangle, column-major in LDS.  Factors ncols pivot columns and
     // applies their Schur update to the trailing (m - ncols) block.
+    __shared__ double thr[TB];
     const int ti = threadIdx.x % 64, tj = threadIdx.x / 64;
+    if (threadIdx.x < ncols) thr[threadIdx.x] = pr.thresh(pivot0 + threadIdx.x);
     for (int k = 0; k < ncols; k++) {
         __syncthreads();
         double d = A[k + lda * k];
-        if (!(d > pr.thresh(pivot0 + k))) {
+        if (!(d > thr[k])) {
             if (threadIdx.x == 0 && *bad_local < 0) *bad_local = k;
             d = 1.0;
         }
@@ -202,48 +216,58 @@ __global__ __launch_bounds__(NT) void front_small(const int32_t* __restrict__ li
 // items: potrf (s, k0) packed as two ints; trsm (s, k0, rb); syrk (s, k0, bi, bj)
 constexpr int ST = 128;  // trailing-update tile edge
 
-// Cholesky of the kb x kb diagonal block at (k0, k0): one wave, LDS row-major, lane i owns row i.
+// Cholesky of the kb x kb diagonal block at (k0, k0) by one wave: lane i keeps row i in registers,
+// column k of L is broadcast with lane shuffles (fully unrolled; the 64 pivot thresholds are
+// fetched once, one per lane).  Returns the local index of the first rejected pivot or -1.
+__device__ __forceinline__ int wave_potrf(double (&a)[TB], int kb, int lane, double thr) {
+    int bad = -1;
+#pragma unroll
+    for (int k = 0; k < TB; k++) {
+        if (k < kb) {
+            double d = __shfl(a[k], k);
+            if (!(d > __shfl(thr, k))) {
+                if (bad < 0) bad = k;
+                d = 1.0;
+            }
+            const double r = sqrt(d);
+            const double lik = lane == k ? r : a[k] / r;
+            a[k] = lik;
+#pragma unroll
+            for (int j = k + 1; j < TB; j++) {
+                if (j < kb) {
+                    const double ljk = __shfl(lik, j);
+                    if (lane >= j) a[j] -= lik * ljk;
+                }
+            }
+        }
+    }
+    return bad;
+}
+
+// Cholesky of the diagonal block of one blocked step (one wave per front).
 __global__ __launch_bounds__(64) void blk_potrf(const int32_t* __restrict__ it, const int32_t* __restrict__ first,
                                                 const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
                                                 const int64_t* __restrict__ foff, double* __restrict__ fronts,
                                                 int32_t* __restrict__ status, PivotRef pr) {
-    __shared__ double A[TB * (TB + 1)];
     const int s = it[2 * blockIdx.x], k0 = it[2 * blockIdx.x + 1];
     const int m = mrows[s];
     const int kb = min(TB, ncol[s] - k0);
     double* F = fronts + foff[s] + (int64_t)k0 + (int64_t)m * k0;
-    const int i = threadIdx.x;
-    for (int e = i; e < kb * kb; e += 64) {
-        const int r = e % kb, c = e / kb;
-        if (r >= c) A[r * (TB + 1) + c] = F[r + (int64_t)m * c];
-    }
-    __syncthreads();
-    int bad = -1;
-    for (int k = 0; k < kb; k++) {
-        double d = A[k * (TB + 1) + k];
-        if (!(d > pr.thresh(first[s] + k0 + k))) {
-            if (bad < 0) bad = k;
-            d = 1.0;
-        }
-        const double r = sqrt(d);
-        __syncthreads();
-        if (i == k) A[k * (TB + 1) + k] = r;
-        if (i > k && i < kb) A[i * (TB + 1) + k] /= r;
-        __syncthreads();
-        if (i > k && i < kb) {
-            const double lik = A[i * (TB + 1) + k];
-            for (int j = k + 1; j <= i; j++) A[i * (TB + 1) + j] -= lik * A[j * (TB + 1) + k];
-        }
-        __syncthreads();
-    }
-    for (int e = i; e < kb * kb; e += 64) {
-        const int r = e % kb, c = e / kb;
-        if (r >= c) F[r + (int64_t)m * c] = A[r * (TB + 1) + c];
-    }
-    if (i == 0 && bad >= 0) status[s] = min(status[s], first[s] + k0 + bad);
+    const int lane = threadIdx.x;
+    const int p0 = first[s] + k0;
+    const double thr = lane < kb ? pr.thresh(p0 + lane) : 0.0;
+    double a[TB];
+#pragma unroll
+    for (int j = 0; j < TB; j++) a[j] = (j < kb && lane < kb && j <= lane) ? F[lane + (int64_t)m * j] : 0.0;
+    const int bad = wave_potrf(a, kb, lane, thr);
+#pragma unroll
+    for (int j = 0; j < TB; j++)
+        if (j < kb && lane < kb && j <= lane) F[lane + (int64_t)m * j] = a[j];
+    if (lane == 0 && bad >= 0) status[s] = min(status[s], p0 + bad);
 }
 
-// X <- X L_D^{-T}: one thread per panel row (256 rows per work-group), row kept in registers.
+// X <- X L_D^{-T} below the diagonal block: one thread per panel row (256 rows per work-group) with
+// the row in registers, L_D staged in LDS and read as broadcasts; two accumulators per inner product.
 __global__ __launch_bounds__(NT) void blk_trsm(const int32_t* __restrict__ it, const int32_t* __restrict__ ncol,
                                                const int32_t* __restrict__ mrows, const int64_t* __restrict__ foff,
                                                double* __restrict__ fronts) {
@@ -251,13 +275,13 @@ __global__ __launch_bounds__(NT) void blk_trsm(const int32_t* __restrict__ it, c
     const int s = it[3 * blockIdx.x], k0 = it[3 * blockIdx.x + 1], rb = it[3 * blockIdx.x + 2];
     const int m = mrows[s];
     const int kb = min(TB, ncol[s] - k0);
-    const int row = k0 + kb + rb * NT + threadIdx.x;
     double* F = fronts + foff[s];
     for (int e = threadIdx.x; e < kb * kb; e += NT) {
         const int r = e % kb, c = e / kb;
         if (r >= c) Ld[r * (TB + 1) + c] = F[(int64_t)(k0 + r) + (int64_t)m * (k0 + c)];
     }
     __syncthreads();
+    const int row = k0 + kb + rb * NT + threadIdx.x;
     if (row >= m) return;
     double x[TB];
 #pragma unroll
@@ -265,10 +289,14 @@ __global__ __launch_bounds__(NT) void blk_trsm(const int32_t* __restrict__ it, c
 #pragma unroll
     for (int j = 0; j < TB; j++) {
         if (j < kb) {
-            double acc = x[j];
+            double acc0 = x[j], acc1 = 0.0;
 #pragma unroll
-            for (int t = 0; t < j; t++) acc -= x[t] * Ld[j * (TB + 1) + t];
-            x[j] = acc / Ld[j * (TB + 1) + j];
+            for (int t = 0; t + 1 < j; t += 2) {
+                acc0 -= x[t] * Ld[j * (TB + 1) + t];
+                acc1 -= x[t + 1] * Ld[j * (TB + 1) + t + 1];
+            }
+            if (j & 1) acc0 -= x[j - 1] * Ld[j * (TB + 1) + j - 1];
+            x[j] = (acc0 + acc1) / Ld[j * (TB + 1) + j];
         }
     }
 #pragma unroll
@@ -327,25 +355,28 @@ __global__ __launch_bounds__(NT) void blk_syrk(const int32_t* __restrict__ it, c
                 for (int a = 0; a < 4; a++) av[a] = Pi[t + lk][qr + 16 * a + li];
 #pragma unroll
                 for (int b = 0; b < 4; b++) bv[b] = Pj[t + lk][qc + 16 * b + li];
+                // operands swapped: the product block is C^T, so a 16-lane group holds 16 consecutive
+                // rows of one column of C (coalesced column-major writes)
 #pragma unroll
                 for (int a = 0; a < 4; a++)
 #pragma unroll
                     for (int b = 0; b < 4; b++)
-                        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+                        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[b], av[a], acc[a][b], 0, 0, 0);
             }
         }
     }
     if (!active) return;
     double* Fw = fronts + foff[s];
-    // D layout of the 16x16x4 f64 MFMA: item r of a lane is row (lane / 16) + 4 r, column lane % 16
+    // D layout of the 16x16x4 f64 MFMA: item r of a lane is row (lane / 16) + 4 r, column lane % 16 of
+    // the product block, here C^T: C row = lane % 16, C column = (lane / 16) + 4 r
 #pragma unroll
     for (int a = 0; a < 4; a++)
 #pragma unroll
         for (int b = 0; b < 4; b++)
 #pragma unroll
             for (int r = 0; r < 4; r++) {
-                const int i = qr + 16 * a + (lane / 16) + 4 * r;
-                const int j = qc + 16 * b + (lane % 16);
+                const int i = qr + 16 * a + (lane % 16);
+                const int j = qc + 16 * b + (lane / 16) + 4 * r;
                 const int gi = ri0 + i, gj = rj0 + j;
                 if (i < nri && j < nrj && gi >= gj) Fw[(int64_t)gi + (int64_t)m * gj] -= acc[a][b][r];
             }
@@ -764,6 +795,15 @@ static void build_numeric_plan(chol_sym* C, const std::vector<int32_t>& colptr, 
             st.p1 = (int32_t)pot.size() / 2;
             st.t1 = (int32_t)trs.size() / 3;
             st.s1 = (int32_t)syr.size() / 4;
+            double fl = 0;
+            for (int q = C->lvl_ptr[l]; q < C->lvl_ptr[l + 1]; q++) {
+                int s = C->lvl_sn[q];
+                int m = C->h_mrows[s], nn = C->h_ncol[s];
+                if (m <= TB || k * TB >= nn) continue;
+                double kb = std::min(TB, nn - k * TB), r = m - k * TB - kb;
+                fl += r * (r + 1) * kb;  // symmetric rank-kb update of an r x r lower triangle
+            }
+            C->step_syrk_flops.push_back(fl);
             C->steps.push_back(st);
         }
         C->lvl_step_ptr[l + 1] = (int32_t)C->steps.size();
@@ -899,39 +939,74 @@ extern "C" int chol_supernode_rows(const chol_sym* C, int64_t* rows_ptr, int32_t
 namespace opf {
 
 // Enqueue the numeric factorization (no synchronisation).
+static void tmark(chol_sym* C, hipStream_t st, int cat) {
+    if (!C->timing) return;
+    if (C->ev_used == C->ev_pool.size()) {
+        hipEvent_t e;
+        OPF_HIP(hipEventCreate(&e));
+        C->ev_pool.push_back(e);
+        C->ev_cat.push_back(0);
+    }
+    C->ev_cat[C->ev_used] = cat;
+    OPF_HIP(hipEventRecord(C->ev_pool[C->ev_used++], st));
+}
+
+// After a synchronisation: fold the recorded (start, end) event pairs into the per-category totals.
+static void tcollect(chol_sym* C) {
+    if (!C->timing) return;
+    for (size_t i = 0; i + 1 < C->ev_used; i += 2) {
+        float ms = 0;
+        OPF_HIP(hipEventElapsedTime(&ms, C->ev_pool[i], C->ev_pool[i + 1]));
+        C->t_ms[C->ev_cat[i]] += ms;
+        C->t_launch[C->ev_cat[i]]++;
+    }
+    C->ev_used = 0;
+}
+
 void chol_factor_enqueue(chol_sym* C, const double* kval, hipStream_t st, double pivot_tol) {
     C->dev.run();
     const PivotRef pr{kval, C->kdiagpos.p, pivot_tol};
     for (int l = 0; l < C->nlevels; l++) {
         int t0 = C->asm_ptr[l], t1 = C->asm_ptr[l + 1];
         if (t1 > t0) {
+            tmark(C, st, 0);
             hipLaunchKernelGGL(front_assemble, dim3(t1 - t0), dim3(NT), 0, st, t0, C->tile_sn.p, C->tile_rc.p,
                                C->tile_kptr.p, C->tile_k.p, C->tile_kpos.p, kval, C->ncol.p, C->mrows.p, C->foff.p,
                                C->child_ptr.p, C->child.p, C->rel_off.p, C->rel.p, C->fronts.p);
             OPF_LAUNCH_CHECK();
+            tmark(C, st, 0);
         }
         int s0 = C->lvl_small_ptr[l], s1 = C->lvl_small_ptr[l + 1];
         if (s1 > s0) {
+            tmark(C, st, 1);
             hipLaunchKernelGGL(front_small, dim3(s1 - s0), dim3(NT), 0, st, C->lvl_small_d.p + s0, C->first.p,
                                C->ncol.p, C->mrows.p, C->foff.p, C->fronts.p, C->status.p, pr);
             OPF_LAUNCH_CHECK();
+            tmark(C, st, 1);
         }
         for (int q = C->lvl_step_ptr[l]; q < C->lvl_step_ptr[l + 1]; q++) {
             const chol_sym::Step& S = C->steps[q];
             if (S.p1 > S.p0) {
+                tmark(C, st, 2);
                 hipLaunchKernelGGL(blk_potrf, dim3(S.p1 - S.p0), dim3(64), 0, st, C->potrf_it.p + 2 * S.p0,
                                    C->first.p, C->ncol.p, C->mrows.p, C->foff.p, C->fronts.p, C->status.p, pr);
                 OPF_LAUNCH_CHECK();
+                tmark(C, st, 2);
             }
             if (S.t1 > S.t0) {
+                tmark(C, st, 3);
                 hipLaunchKernelGGL(blk_trsm, dim3(S.t1 - S.t0), dim3(NT), 0, st, C->trsm_it.p + 3 * S.t0, C->ncol.p,
                                    C->mrows.p, C->foff.p, C->fronts.p);
                 OPF_LAUNCH_CHECK();
+                tmark(C, st, 3);
             }
             if (S.s1 > S.s0) {
+                tmark(C, st, 4);
                 hipLaunchKernelGGL(blk_syrk, dim3(S.s1 - S.s0), dim3(NT), 0, st, C->syrk_it.p + 4 * S.s0, C->ncol.p,
                                    C->mrows.p, C->foff.p, C->fronts.p);
                 OPF_LAUNCH_CHECK();
+                tmark(C, st, 4);
+                if (C->timing) C->t_flops[4] += C->step_syrk_flops[q];
             }
         }
     }
@@ -952,6 +1027,7 @@ int chol_factor_sync(chol_sym* C, const double* kval, hipStream_t st, double piv
     std::vector<int32_t> stat(ns);
     OPF_HIP(hipMemcpyAsync(stat.data(), C->status.p, ns * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     OPF_HIP(hipStreamSynchronize(st));
+    tcollect(C);
     int bad_level = INT_MAX, bad = -1;
     for (int s = 0; s < ns; s++)
         if (stat[s] != INT_MAX) {
@@ -1079,6 +1155,30 @@ extern "C" int chol_export_factor(chol_sym* C, int64_t* lp, int32_t* li, double*
                 }
                 lp[f + jc + 1] = q;
             }
+        }
+    });
+}
+
+extern "C" int chol_timing(chol_sym* C, int enable) {
+    return guarded([&] {
+        OPF_CHECK(C, OPF_E_INVALID, "chol_timing: null handle");
+        C->timing = enable != 0;
+        C->ev_used = 0;
+        for (int q = 0; q < 5; q++) {
+            C->t_ms[q] = 0;
+            C->t_launch[q] = 0;
+            C->t_flops[q] = 0;
+        }
+    });
+}
+
+extern "C" int chol_timing_read(const chol_sym* C, double* ms, int64_t* launches, double* flops) {
+    return guarded([&] {
+        OPF_CHECK(C, OPF_E_INVALID, "chol_timing_read: null handle");
+        for (int q = 0; q < 5; q++) {
+            if (ms) ms[q] = C->t_ms[q];
+            if (launches) launches[q] = C->t_launch[q];
+            if (flops) flops[q] = C->t_flops[q];
         }
     });
 }

@@ -29,7 +29,8 @@ EXPORTED = [
     "opf_eval_derivs", "kkt_pattern", "kkt_condense", "chol_default_options", "chol_analyze", "chol_destroy",
     "chol_info", "chol_perm", "chol_etree", "chol_supernodes", "chol_supernode_rows", "chol_factor", "chol_solve",
     "chol_export_factor", "ipm_default_options", "ipm_create", "ipm_destroy", "ipm_step", "ipm_solve",
-    "ipm_get_iterate", "ipm_chol", "ipm_get_state", "ipm_set_state", "ipm_direction",
+    "ipm_get_iterate", "ipm_chol", "ipm_get_state", "ipm_set_state", "ipm_direction", "chol_timing",
+    "chol_timing_read",
 ]
 
 
@@ -100,6 +101,8 @@ def lib():
         L.chol_factor.argtypes = [VP, VP, VP, I32P]
         L.chol_solve.argtypes = [VP, VP, VP, ctypes.c_int32, VP]
         L.chol_export_factor.argtypes = [VP, I64P, I32P, F64P]
+        L.chol_timing.argtypes = [VP, ctypes.c_int]
+        L.chol_timing_read.argtypes = [VP, F64P, I64P, F64P]
         L.ipm_default_options.argtypes = [ctypes.POINTER(IpmOptions)]
         L.ipm_default_options.restype = None
         L.ipm_create.argtypes = [VP, ctypes.POINTER(IpmOptions), ctypes.POINTER(CholOptions), VP, ctypes.POINTER(VP)]
@@ -298,6 +301,18 @@ class Cholesky:
         nrhs = 1 if b.dim() == 1 else b.shape[1]
         _check(lib().chol_solve(self._h, _dptr(b), _dptr(x), nrhs, _stream(stream)), "chol_solve")
         return x
+
+    TIMING_CATEGORIES = ("assembly", "small_fronts", "diag_block", "panel_solve", "trailing_update")
+
+    def timing(self, enable=True):
+        _check(lib().chol_timing(self._h, int(bool(enable))), "chol_timing")
+
+    def timing_read(self):
+        ms = np.zeros(5)
+        nl = np.zeros(5, np.int64)
+        fl = np.zeros(5)
+        _check(lib().chol_timing_read(self._h, _p(ms, F64P), _p(nl, I64P), _p(fl, F64P)), "chol_timing_read")
+        return {k: {"ms": ms[i], "launches": int(nl[i]), "flops": fl[i]} for i, k in enumerate(self.TIMING_CATEGORIES)}
 
     def export_factor(self, values=True):
         lp = np.zeros(self.n + 1, np.int64)
