@@ -216,16 +216,26 @@ __global__ __launch_bounds__(NT) void front_small(const int32_t* __restrict__ li
 // items: potrf (s, k0) packed as two ints; trsm (s, k0, rb); syrk (s, k0, bi, bj)
 constexpr int ST = 128;  // trailing-update tile edge
 
-// Cholesky of the kb x kb diagonal block at (k0, k0) by one wave: lane i keeps row i in registers,
-// column k of L is broadcast with lane shuffles (fully unrolled; the 64 pivot thresholds are
-// fetched once, one per lane).  Returns the local index of the first rejected pivot or -1.
+// Value of v held by lane l, read into scalar registers (l is a compile-time constant after unrolling).
+__device__ __forceinline__ double lane_value(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Cholesky of the kb x kb diagonal block at (k0, k0) by one wave: lane i keeps row i in registers and
+// the entries of column k of L are read lane by lane into scalar registers, so the update of a step
+// is a run of independent FMAs with no LDS round trip.  Rows >= kb are zero on entry and stay zero,
+// which makes the inner loop safe to run over the full tile width; entries above the diagonal are
+// updated too (never stored).  Returns the local index of the first rejected pivot or -1.
 __device__ __forceinline__ int wave_potrf(double (&a)[TB], int kb, int lane, double thr) {
     int bad = -1;
 #pragma unroll
     for (int k = 0; k < TB; k++) {
         if (k < kb) {
-            double d = __shfl(a[k], k);
-            if (!(d > __shfl(thr, k))) {
+            double d = lane_value(a[k], k);
+            if (!(d > lane_value(thr, k))) {
                 if (bad < 0) bad = k;
                 d = 1.0;
             }
@@ -233,12 +243,7 @@ __device__ __forceinline__ int wave_potrf(double (&a)[TB], int kb, int lane, dou
             const double lik = lane == k ? r : a[k] / r;
             a[k] = lik;
 #pragma unroll
-            for (int j = k + 1; j < TB; j++) {
-                if (j < kb) {
-                    const double ljk = __shfl(lik, j);
-                    if (lane >= j) a[j] -= lik * ljk;
-                }
-            }
+            for (int j = k + 1; j < TB; j++) a[j] -= lik * lane_value(lik, j);
         }
     }
     return bad;
