@@ -98,7 +98,9 @@ def main():
     ms = 1e3 * elapsed / args.steps
     fac_ms = np.mean([i["t_factor"] / max(i["factorizations"], 1) for i in timed])
     stage = {k: float(np.mean([i[k] for i in timed])) for k in ("t_ad", "t_assembly", "t_factor", "t_solve")}
-    log(f"[bench] {args.steps} iterations in {elapsed:.3f}s = {ms:.2f} ms/iter; stages (ms) {stage}")
+    log(f"[bench] {args.steps} iterations in {elapsed:.3f}s = {ms:.2f} ms/iter; stages (ms) {stage}; "
+        f"refinement steps/iter {np.mean([i['ir_steps'] for i in timed]):.2f}, "
+        f"factorizations/iter {np.mean([i['factorizations'] for i in timed]):.2f}")
     factor_tflops = C.flops / (fac_ms * 1e-3) / 1e12
     tu = kt["trailing_update"]
     avg_ms = tu["ms"] / max(tu["launches"], 1)

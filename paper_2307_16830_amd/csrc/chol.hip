@@ -72,6 +72,10 @@ struct chol_sym {
     DBuf<int32_t> potrf_it, trsm_it, syrk_it;  // packed items
     DBuf<int32_t> status;
     DBuf<double> fronts, upd, work, ybuf;
+    // sync-free solves of wide fronts: one ready flag per 64-block, compared with a per-sweep epoch
+    std::vector<int64_t> h_flag_off;  // per supernode (wide fronts only)
+    DBuf<int32_t> sflags, sfault;
+    int32_t epoch = 0;
     Deferred dev;  // pending uploads, run at the first device use
     // optional per-category kernel timing (assemble, small, potrf, trsm, syrk)
     bool timing = false;
@@ -440,22 +444,41 @@ __global__ __launch_bounds__(NT) void solve_fwd(const int32_t* __restrict__ list
     }
 }
 
-// Backward sweep for one front: x(own) = L11^{-T} (y(own) - L21^T x(rows below)).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Backward sweep for one front: x(own) = L11^{-T} (y(own) - L21^T x(rows below)).  The products with
+// the rows below run one wave per column (lanes over rows, coalesced) on row chunks staged in LDS.
+constexpr int XCH = 1024;  // rows per staged chunk
+
 __global__ __launch_bounds__(NT) void solve_bwd(const int32_t* __restrict__ list, const int32_t* __restrict__ first,
                                                 const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
                                                 const int64_t* __restrict__ foff, const int64_t* __restrict__ roff,
                                                 const int32_t* __restrict__ rows, const double* __restrict__ fronts,
                                                 double* __restrict__ work, double* __restrict__ y) {
+    __shared__ double xb[XCH];
     const int s = list[blockIdx.x];
     const int m = mrows[s], nn = ncol[s], f = first[s];
     const int32_t* R = rows + roff[s];
     const double* L = fronts + foff[s];
     double* w = work + roff[s];
-    for (int j = threadIdx.x; j < nn; j += NT) {
-        double acc = y[f + j];
-        const double* col = L + (int64_t)m * j;
-        for (int i = nn; i < m; i++) acc -= col[i] * y[R[i]];
-        w[j] = acc;
+    const int wv = threadIdx.x / 64, ln = threadIdx.x % 64;
+    for (int j = threadIdx.x; j < nn; j += NT) w[j] = y[f + j];
+    for (int r0 = nn; r0 < m; r0 += XCH) {
+        const int nr = min(XCH, m - r0);
+        __syncthreads();
+        for (int t = threadIdx.x; t < nr; t += NT) xb[t] = y[R[r0 + t]];
+        __syncthreads();
+        for (int j = wv; j < nn; j += NT / 64) {
+            const double* col = L + (int64_t)m * j + r0;
+            double acc = 0.0;
+            for (int t = ln; t < nr; t += 64) acc += col[t] * xb[t];
+            acc = wave_sum(acc);
+            if (ln == 0) w[j] -= acc;
+        }
     }
     __syncthreads();
     for (int j = nn - 1; j >= 0; j--) {
@@ -468,12 +491,51 @@ __global__ __launch_bounds__(NT) void solve_bwd(const int32_t* __restrict__ list
     for (int j = threadIdx.x; j < nn; j += NT) y[f + j] = w[j];
 }
 
-// ---------------------------------------------------------------- blocked solves for wide fronts
-// A front with many pivots is solved in 64-column blocks, one launch per block, with the rows
-// (forward) or pivot columns (backward) spread over many work-groups.  Every work-group first
-// solves the 64 x 64 diagonal block redundantly with one wave and lane shuffles, so no
-// cross-work-group synchronisation is needed inside a launch.
-constexpr int WIDE = 256;  // fronts with at least this many pivots use the blocked solves
+// ---------------------------------------------------------------- sync-free solves for wide fronts
+// A front with many pivots is solved by one launch per sweep whose work-groups each own a 64-row
+// (forward) or 64-column (backward) block of the front.  A block's work-group multiplies its part of
+// L with every solved block as soon as that block's ready flag carries the sweep's epoch, then
+// solves with its own diagonal block in registers (one wave, pivots read lane by lane) and publishes
+// its block and flag.  Every wait is on a lower-numbered work-group, and work-groups are dispatched
+// in index order, so a waiting work-group never holds back the one it waits for.  Solved blocks and
+// flags go through device-coherent (agent-scope) stores and loads, because the work-groups of a
+// launch sit on different dies with separate L2 caches.  A wait is bounded: past the spin limit the
+// fault word is raised and the work-group goes on (the result is then invalid and reported).
+constexpr int WIDE = 256;  // fronts with at least this many pivots use the sync-free solves
+constexpr int SB = 64;     // block edge of the sync-free solves
+
+__global__ void fill_i32(int64_t n, int32_t* __restrict__ p, int32_t v) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) p[k] = v;
+}
+
+__device__ __forceinline__ void store_coherent(double* p, double v) {
+    __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), (unsigned long long)__double_as_longlong(v),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ double load_coherent(const double* p) {
+    return __longlong_as_double((long long)__hip_atomic_load(
+        reinterpret_cast<unsigned long long*>(const_cast<double*>(p)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
+// Spin until *flag == epoch.  Once one wait of a work-group has timed out (alive = false) its later
+// waits return at once, so a work-group spends at most one spin limit (about a second) waiting.
+__device__ __forceinline__ void wait_flag(int32_t* flag, int32_t epoch, int32_t* fault, bool& alive) {
+    if (!alive) return;
+    for (int it = 0; it < (1 << 20); it++) {
+        if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch) return;
+        __builtin_amdgcn_s_sleep(2);
+    }
+    alive = false;
+    __hip_atomic_store(fault, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Publish a solved block: all its stores complete before the flag is raised.
+__device__ __forceinline__ void publish(int32_t* flag, int32_t epoch, bool leader) {
+    __builtin_amdgcn_s_waitcnt(0);
+    if (leader) __hip_atomic_store(flag, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // forward, step 0: w = [y(own rows), 0] + children's partial results (one work-group per front)
 __global__ __launch_bounds__(NT) void sfwd_gather(const int32_t* __restrict__ list, const int32_t* __restrict__ first,
@@ -499,110 +561,143 @@ __global__ __launch_bounds__(NT) void sfwd_gather(const int32_t* __restrict__ li
     }
 }
 
-// forward, one 64-column block: z = L_bb^{-1} w_b (written to y), w(rows below) -= L(rows, b) z
-__global__ __launch_bounds__(NT) void sfwd_block(int s, int k0, const int32_t* __restrict__ first,
-                                                 const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
-                                                 const int64_t* __restrict__ foff, const int64_t* __restrict__ roff,
-                                                 const double* __restrict__ fronts, double* __restrict__ work,
-                                                 double* __restrict__ y) {
-    __shared__ double Ld[TB * (TB + 1)];
-    __shared__ double z[TB];
-    const int m = mrows[s], nn = ncol[s];
-    const int kb = min(TB, nn - k0);
-    const double* L = fronts + foff[s];
-    double* w = work + roff[s];
-    for (int e = threadIdx.x; e < kb * kb; e += NT) {
-        const int r = e % kb, c = e / kb;
-        if (r >= c) Ld[r * (TB + 1) + c] = L[(int64_t)(k0 + r) + (int64_t)m * (k0 + c)];
-    }
-    __syncthreads();
-    if (threadIdx.x < 64) {
-        const int lane = threadIdx.x;
-        double wi = lane < kb ? w[k0 + lane] : 0.0;
-        const double dii = lane < kb ? Ld[lane * (TB + 1) + lane] : 1.0;
-        for (int j = 0; j < kb; j++) {
-            const double zj = __shfl(wi / dii, j);
-            if (lane == j) wi = zj;
-            if (lane > j && lane < kb) wi -= Ld[lane * (TB + 1) + j] * zj;
-        }
-        if (lane < kb) z[lane] = wi;
-    }
-    __syncthreads();
-    if (blockIdx.x == 0)
-        for (int j = threadIdx.x; j < kb; j += NT) y[first[s] + k0 + j] = z[j];
-    const int i = k0 + kb + blockIdx.x * NT + threadIdx.x;
-    if (i < m) {
-        double acc = w[i];
-        for (int j = 0; j < kb; j++) acc -= L[(int64_t)i + (int64_t)m * (k0 + j)] * z[j];
-        w[i] = acc;
-    }
-}
-
-// forward, last step: the rows below the pivots become this front's partial result
-__global__ void sfwd_finish(int s, const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
-                            const int64_t* __restrict__ roff, const int64_t* __restrict__ uoff,
-                            const double* __restrict__ work, double* __restrict__ upd) {
-    const int m = mrows[s], nn = ncol[s];
-    const int t = blockIdx.x * NT + threadIdx.x;
-    if (t < m - nn) upd[uoff[s] + t] = work[roff[s] + nn + t];
-}
-
-// backward, step 0: t = y(own) - L21^T x(rows below), one thread per pivot column
-__global__ __launch_bounds__(NT) void sbwd_init(int s, const int32_t* __restrict__ first,
-                                                const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
-                                                const int64_t* __restrict__ foff, const int64_t* __restrict__ roff,
-                                                const int32_t* __restrict__ rows, const double* __restrict__ fronts,
-                                                double* __restrict__ work, const double* __restrict__ y) {
+// forward sweep of one wide front.  Work-group g < nblk owns pivot rows [64g, 64g + 64): it subtracts
+// L(rows, block c) z_c for every c < g, solves with L(g, g) and publishes z_g in y.  The remaining
+// work-groups own 64-row blocks of the rows below the pivots and write their partial result to upd.
+// Thread (i, q) = (row in block, quarter of the 64 columns of a block).
+__global__ __launch_bounds__(NT) void wide_fwd(int s, int32_t epoch, int32_t* __restrict__ flags,
+                                               int32_t* __restrict__ fault, const int32_t* __restrict__ first,
+                                               const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
+                                               const int64_t* __restrict__ foff, const int64_t* __restrict__ roff,
+                                               const int64_t* __restrict__ uoff, const double* __restrict__ fronts,
+                                               const double* __restrict__ work, double* __restrict__ upd,
+                                               double* __restrict__ y) {
+    __shared__ double zs[SB];
+    __shared__ double red[NT / 64][SB];
     const int m = mrows[s], nn = ncol[s], f = first[s];
-    const int j = blockIdx.x * NT + threadIdx.x;
-    if (j >= nn) return;
-    const int32_t* R = rows + roff[s];
-    const double* col = fronts + foff[s] + (int64_t)m * j;
-    double acc = y[f + j];
-    for (int i = nn; i < m; i++) acc -= col[i] * y[R[i]];
-    work[roff[s] + j] = acc;
+    const int nblk = (nn + SB - 1) / SB;
+    const int g = blockIdx.x;
+    const bool piv = g < nblk;
+    const int r0 = piv ? SB * g : nn + SB * (g - nblk);
+    const int nr = min(SB, (piv ? nn : m) - r0);
+    const int ncb = piv ? g : nblk;
+    const double* L = fronts + foff[s];
+    const int i = threadIdx.x % 64, q = threadIdx.x / 64;
+    const bool rowok = i < nr;
+    const double* Lr = L + (rowok ? r0 + i : 0);  // row r0 + i, column stride m
+    // own diagonal block (row i in registers of wave 0) and reciprocal pivot, read before any wait
+    double a[SB];
+    double rinv = 1.0;
+#pragma unroll
+    for (int j = 0; j < SB; j++) a[j] = (piv && q == 0 && rowok && j < i) ? Lr[(int64_t)m * (r0 + j)] : 0.0;
+    if (piv && q == 0 && rowok) rinv = 1.0 / Lr[(int64_t)m * (r0 + i)];
+    double acc = 0.0;
+    bool alive = true;
+    for (int c = 0; c < ncb; c++) {
+        const int c0 = SB * c, kc = min(SB, nn - c0);
+        double lv[16];
+#pragma unroll
+        for (int jj = 0; jj < 16; jj++) {
+            const int j = 16 * q + jj;
+            lv[jj] = (rowok && j < kc) ? Lr[(int64_t)m * (c0 + j)] : 0.0;
+        }
+        if (threadIdx.x == 0) wait_flag(flags + c, epoch, fault, alive);
+        __syncthreads();
+        if (threadIdx.x < SB) zs[threadIdx.x] = (int)threadIdx.x < kc ? load_coherent(y + f + c0 + threadIdx.x) : 0.0;
+        __syncthreads();
+#pragma unroll
+        for (int jj = 0; jj < 16; jj++) acc += lv[jj] * zs[16 * q + jj];
+    }
+    red[q][i] = acc;
+    __syncthreads();
+    if (q != 0) return;
+    double wi = rowok ? work[roff[s] + r0 + i] - ((red[0][i] + red[1][i]) + (red[2][i] + red[3][i])) : 0.0;
+    if (!piv) {
+        if (rowok) upd[uoff[s] + (r0 - nn) + i] = wi;
+        return;
+    }
+#pragma unroll
+    for (int j = 0; j < SB; j++) {
+        if (j < nr) {
+            const double zj = lane_value(wi * rinv, j);
+            wi = i == j ? zj : (i > j ? wi - a[j] * zj : wi);
+        }
+    }
+    if (rowok) store_coherent(y + f + r0 + i, wi);
+    publish(flags + g, epoch, i == 0);
 }
 
-// backward, one 64-column block (last to first): x_b = L_bb^{-T} t_b (written to y),
-// t(columns before the block) -= L(b, columns)^T x_b
-__global__ __launch_bounds__(NT) void sbwd_block(int s, int k0, const int32_t* __restrict__ first,
-                                                 const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
-                                                 const int64_t* __restrict__ foff, const int64_t* __restrict__ roff,
-                                                 const double* __restrict__ fronts, double* __restrict__ work,
-                                                 double* __restrict__ y) {
-    __shared__ double Ld[TB * (TB + 1)];
-    __shared__ double xb[TB];
-    const int m = mrows[s], nn = ncol[s];
-    const int kb = min(TB, nn - k0);
-    const double* L = fronts + foff[s];
-    double* t = work + roff[s];
-    for (int e = threadIdx.x; e < kb * kb; e += NT) {
-        const int r = e % kb, c = e / kb;
-        if (r >= c) Ld[r * (TB + 1) + c] = L[(int64_t)(k0 + r) + (int64_t)m * (k0 + c)];
-    }
-    __syncthreads();
-    if (threadIdx.x < 64) {
-        const int lane = threadIdx.x;
-        double ti = lane < kb ? t[k0 + lane] : 0.0;
-        const double dii = lane < kb ? Ld[lane * (TB + 1) + lane] : 1.0;
-        for (int j = kb - 1; j >= 0; j--) {
-            const double xj = __shfl(ti / dii, j);
-            if (lane == j) ti = xj;
-            if (lane < j) ti -= Ld[j * (TB + 1) + lane] * xj;
+// backward sweep of one wide front.  Work-group g owns pivot block b = nblk - 1 - g (columns
+// [64b, 64b + 64)): it subtracts L(rows, b)^T x for the rows below the pivots (solved by the
+// ancestors) and for every later block c > b as soon as it is published, then solves with L(b, b)^T
+// and publishes x_b in y.  Thread (j, q) = (column in block, quarter of the 64 rows of a block).
+__global__ __launch_bounds__(NT) void wide_bwd(int s, int32_t epoch, int32_t* __restrict__ flags,
+                                               int32_t* __restrict__ fault, const int32_t* __restrict__ first,
+                                               const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
+                                               const int64_t* __restrict__ foff, const int64_t* __restrict__ roff,
+                                               const int32_t* __restrict__ rows, const double* __restrict__ fronts,
+                                               double* __restrict__ y) {
+    __shared__ double xs[SB];
+    __shared__ double red[NT / 64][SB];
+    const int m = mrows[s], nn = ncol[s], f = first[s];
+    const int nblk = (nn + SB - 1) / SB;
+    const int g = blockIdx.x;
+    const int b = nblk - 1 - g;
+    const int c0 = SB * b, kb = min(SB, nn - c0);
+    const int32_t* R = rows + roff[s];
+    const int j = threadIdx.x % 64, q = threadIdx.x / 64;
+    const bool colok = j < kb;
+    const double* Lc = fronts + foff[s] + (int64_t)m * (c0 + (colok ? j : 0));  // column c0 + j
+    // own diagonal block (column j in registers of wave 0) and reciprocal pivot
+    double a[SB];
+    double rinv = 1.0;
+#pragma unroll
+    for (int t = 0; t < SB; t++) a[t] = (q == 0 && colok && t > j && t < kb) ? Lc[c0 + t] : 0.0;
+    if (q == 0 && colok) rinv = 1.0 / Lc[c0 + j];
+    double acc = 0.0;
+    for (int r0 = nn; r0 < m; r0 += SB) {
+        const int nr = min(SB, m - r0);
+        double lv[16];
+#pragma unroll
+        for (int ii = 0; ii < 16; ii++) {
+            const int r = 16 * q + ii;
+            lv[ii] = (colok && r < nr) ? Lc[r0 + r] : 0.0;
         }
-        if (lane < kb) xb[lane] = ti;
+        __syncthreads();
+        if (threadIdx.x < SB) xs[threadIdx.x] = (int)threadIdx.x < nr ? y[R[r0 + threadIdx.x]] : 0.0;
+        __syncthreads();
+#pragma unroll
+        for (int ii = 0; ii < 16; ii++) acc += lv[ii] * xs[16 * q + ii];
     }
+    bool alive = true;
+    for (int c = nblk - 1; c > b; c--) {
+        const int cr0 = SB * c, nr = min(SB, nn - cr0);
+        double lv[16];
+#pragma unroll
+        for (int ii = 0; ii < 16; ii++) {
+            const int r = 16 * q + ii;
+            lv[ii] = (colok && r < nr) ? Lc[cr0 + r] : 0.0;
+        }
+        if (threadIdx.x == 0) wait_flag(flags + (nblk - 1 - c), epoch, fault, alive);
+        __syncthreads();
+        if (threadIdx.x < SB) xs[threadIdx.x] = (int)threadIdx.x < nr ? load_coherent(y + f + cr0 + threadIdx.x) : 0.0;
+        __syncthreads();
+#pragma unroll
+        for (int ii = 0; ii < 16; ii++) acc += lv[ii] * xs[16 * q + ii];
+    }
+    red[q][j] = acc;
     __syncthreads();
-    if (blockIdx.x == 0)
-        for (int j = threadIdx.x; j < kb; j += NT) y[first[s] + k0 + j] = xb[j];
-    const int j = blockIdx.x * NT + threadIdx.x;
-    if (j < k0) {
-        double acc = t[j];
-        const double* col = L + (int64_t)m * j + k0;
-        for (int r = 0; r < kb; r++) acc -= col[r] * xb[r];
-        t[j] = acc;
+    if (q != 0) return;
+    double tj = colok ? y[f + c0 + j] - ((red[0][j] + red[1][j]) + (red[2][j] + red[3][j])) : 0.0;
+#pragma unroll
+    for (int t = SB - 1; t >= 0; t--) {
+        if (t < kb) {
+            const double xt = lane_value(tj * rinv, t);
+            tj = j == t ? xt : (j < t ? tj - a[t] * xt : tj);
+        }
     }
-    (void)m;
+    if (colok) store_coherent(y + f + c0 + j, tj);
+    publish(flags + g, epoch, j == 0);
 }
 
 }  // namespace
@@ -848,6 +943,15 @@ static void build_numeric_plan(chol_sym* C, const std::vector<int32_t>& colptr, 
     C->dev.alloc(C->upd, std::max<int64_t>(uo, 1));
     C->dev.alloc(C->work, std::max<int64_t>(C->h_roff[ns], 1));
     C->dev.alloc(C->ybuf, std::max(n, 1));
+    C->h_flag_off.assign(ns, -1);
+    int64_t nflags = 0;
+    for (int s = 0; s < ns; s++)
+        if (C->h_ncol[s] >= WIDE) {
+            C->h_flag_off[s] = nflags;
+            nflags += (C->h_ncol[s] + SB - 1) / SB;
+        }
+    C->dev.upload(C->sflags, std::vector<int32_t>(std::max<int64_t>(nflags, 1), 0));
+    C->dev.upload(C->sfault, std::vector<int32_t>(1, 0));
 }
 
 extern "C" void chol_default_options(chol_options* o) {
@@ -1050,6 +1154,13 @@ void chol_solve_enqueue(chol_sym* C, const double* b, double* x, hipStream_t st)
     C->dev.run();
     const int n = C->n;
     double* y = C->ybuf.p;
+    if (C->epoch > INT32_MAX - 4) {  // epochs restart from 0 once every flag is cleared
+        const int64_t nf = C->sflags.n;
+        hipLaunchKernelGGL(fill_i32, dim3(ceil_div(nf, 256)), dim3(256), 0, st, nf, C->sflags.p, 0);
+        OPF_LAUNCH_CHECK();
+        C->epoch = 0;
+    }
+    const int32_t ef = ++C->epoch, eb = ++C->epoch;
     hipLaunchKernelGGL(permute_in, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, C->perm.p, b, y);
     OPF_LAUNCH_CHECK();
     for (int l = 0; l < C->nlevels; l++) {
@@ -1069,18 +1180,11 @@ void chol_solve_enqueue(chol_sym* C, const double* b, double* x, hipStream_t st)
             for (int q = w0; q < w1; q++) {
                 const int s = C->lvl_wide[q];
                 const int m = C->h_mrows[s], nn = C->h_ncol[s];
-                for (int k0 = 0; k0 < nn; k0 += TB) {
-                    const int kb = std::min(TB, nn - k0);
-                    const unsigned g = std::max(1u, ceil_div(m - k0 - kb, NT));
-                    hipLaunchKernelGGL(sfwd_block, dim3(g), dim3(NT), 0, st, s, k0, C->first.p, C->ncol.p,
-                                       C->mrows.p, C->foff.p, C->roff.p, C->fronts.p, C->work.p, y);
-                    OPF_LAUNCH_CHECK();
-                }
-                if (m > nn) {
-                    hipLaunchKernelGGL(sfwd_finish, dim3(ceil_div(m - nn, NT)), dim3(NT), 0, st, s, C->ncol.p,
-                                       C->mrows.p, C->roff.p, C->uoff.p, C->work.p, C->upd.p);
-                    OPF_LAUNCH_CHECK();
-                }
+                const int g = (nn + SB - 1) / SB + (m - nn + SB - 1) / SB;
+                hipLaunchKernelGGL(wide_fwd, dim3(g), dim3(NT), 0, st, s, ef, C->sflags.p + C->h_flag_off[s],
+                                   C->sfault.p, C->first.p, C->ncol.p, C->mrows.p, C->foff.p, C->roff.p, C->uoff.p,
+                                   C->fronts.p, C->work.p, C->upd.p, y);
+                OPF_LAUNCH_CHECK();
             }
         }
     }
@@ -1089,17 +1193,10 @@ void chol_solve_enqueue(chol_sym* C, const double* b, double* x, hipStream_t st)
         for (int q = w0; q < w1; q++) {
             const int s = C->lvl_wide[q];
             const int nn = C->h_ncol[s];
-            hipLaunchKernelGGL(sbwd_init, dim3(ceil_div(nn, NT)), dim3(NT), 0, st, s, C->first.p, C->ncol.p,
-                               C->mrows.p, C->foff.p, C->roff.p, C->rows.p, C->fronts.p, C->work.p, y);
+            hipLaunchKernelGGL(wide_bwd, dim3((nn + SB - 1) / SB), dim3(NT), 0, st, s, eb,
+                               C->sflags.p + C->h_flag_off[s], C->sfault.p, C->first.p, C->ncol.p, C->mrows.p,
+                               C->foff.p, C->roff.p, C->rows.p, C->fronts.p, y);
             OPF_LAUNCH_CHECK();
-            const int nblk = (nn + TB - 1) / TB;
-            for (int bk = nblk - 1; bk >= 0; bk--) {
-                const int k0 = bk * TB;
-                const unsigned g = std::max(1u, ceil_div(k0, NT));
-                hipLaunchKernelGGL(sbwd_block, dim3(g), dim3(NT), 0, st, s, k0, C->first.p, C->ncol.p, C->mrows.p,
-                                   C->foff.p, C->roff.p, C->fronts.p, C->work.p, y);
-                OPF_LAUNCH_CHECK();
-            }
         }
         int q0 = C->lvl_narrow_ptr[l], q1 = C->lvl_narrow_ptr[l + 1];
         if (q1 > q0) {
@@ -1110,6 +1207,15 @@ void chol_solve_enqueue(chol_sym* C, const double* b, double* x, hipStream_t st)
     }
     hipLaunchKernelGGL(permute_out, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, C->perm.p, y, x);
     OPF_LAUNCH_CHECK();
+}
+
+// Raised by a sync-free solve whose wait exceeded its bound (the solve result is invalid).
+int chol_solve_fault(chol_sym* C, hipStream_t st) {
+    if (C->h_flag_off.empty()) return 0;
+    int32_t v = 0;
+    OPF_HIP(hipMemcpyAsync(&v, C->sfault.p, sizeof v, hipMemcpyDeviceToHost, st));
+    OPF_HIP(hipStreamSynchronize(st));
+    return v;
 }
 
 }  // namespace opf
@@ -1132,6 +1238,8 @@ extern "C" int chol_solve(chol_sym* C, const double* b, double* x, int32_t nrhs,
         OPF_CHECK(C->factored, OPF_E_STATE, "chol_solve: no successful factorization");
         for (int r = 0; r < nrhs; r++)
             chol_solve_enqueue(C, b + (int64_t)r * C->n, x + (int64_t)r * C->n, (hipStream_t)stream);
+        OPF_CHECK(chol_solve_fault(C, (hipStream_t)stream) == 0, OPF_E_DEVICE,
+                  "chol_solve: a wide-front block wait exceeded its bound");
     });
 }
 

@@ -25,6 +25,7 @@ namespace opf {
 void chol_factor_enqueue(chol_sym* C, const double* kval, hipStream_t st, double pivot_tol);
 int chol_factor_sync(chol_sym* C, const double* kval, hipStream_t st, double pivot_tol);
 void chol_solve_enqueue(chol_sym* C, const double* b, double* x, hipStream_t st);
+int chol_solve_fault(chol_sym* C, hipStream_t st);
 }  // namespace opf
 
 using namespace opf;
@@ -768,6 +769,10 @@ static int compute_direction(ipm_state* S, double mu, ipm_iter_info& I) {
         nir++;
     }
     OPF_HIP(hipEventRecord(S->ev[6], st));
+    if (chol_solve_fault(S->C, st)) {
+        set_error("ipm_step: a triangular-solve block wait exceeded its bound");
+        return OPF_E_DEVICE;
+    }
     I.ir_steps = nir;
     I.t_assembly = t_asm;
     I.t_factor = t_fac;

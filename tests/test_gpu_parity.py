@@ -278,6 +278,54 @@ def test_dense_front_blocked_cholesky(n):
     assert np.max(np.abs(L - Lref)) <= 1e-12 * np.max(np.abs(Lref))
 
 
+def _block_system(a, b, c, seed):
+    """SPD matrix of two cliques (a and b vertices) joined by a separator of c vertices adjacent to both:
+    with dense-row detection off, each clique is a front with many pivots and c rows below them."""
+    n = a + b + c
+    rng = np.random.default_rng(seed)
+    A = np.zeros((n, n))
+    sep = list(range(a + b, n))
+    for blk in (range(0, a), range(a, a + b)):
+        idx = np.array(list(blk) + sep, dtype=np.int64)
+        if len(idx):
+            A[np.ix_(idx, idx)] = rng.uniform(-1.0, 1.0, size=(len(idx), len(idx)))
+    A = 0.5 * (A + A.T)
+    np.fill_diagonal(A, 0.0)
+    np.fill_diagonal(A, np.abs(A).sum(axis=1) + 1.0)
+    rows, cols = np.nonzero(np.tril(A))
+    cp, ri = ochol.lower_csc(n, rows, cols)
+    colidx = np.repeat(np.arange(n), np.diff(cp))
+    return A, cp, ri, A[ri, colidx]
+
+
+@pytest.mark.parametrize("sizes", [(333, 0, 0), (1000, 0, 0), (300, 280, 12), (260, 300, 70), (320, 257, 65)])
+def test_wide_front_solves_match_oracle(sizes):
+    """Fronts with >= 256 pivots (with and without rows below them) go through the sync-free block
+    solves; the solution must match the oracle's factor-and-solve on the same matrix."""
+    A, cp, ri, vals = _block_system(*sizes, seed=sum(sizes))
+    n = A.shape[0]
+    o = dict(OPTS, dense_frac=1.0)
+    C = opf().Cholesky(n, cp, ri, opf().chol_options(**o))
+    rp, rows = C.supernode_rows()
+    sp = C.supernodes()
+    widths = np.diff(sp)
+    mrows = np.diff(rp)
+    assert widths.max() >= 256
+    if sizes[2] > 0:
+        assert np.any((widths >= 256) & (mrows > widths))  # a wide front with rows below its pivots
+    sym = ochol.analyze(n, cp, ri, ochol.AnalyzeOptions(**o))
+    oc = ochol.Cholesky(n, cp, ri, sym.perm)
+    assert oc.factor(vals) == -1
+    assert C.factor(dev(vals)) == -1
+    rng = np.random.default_rng(7)
+    for rep in range(3):  # repeated solves reuse the ready flags with new epochs
+        b = rng.normal(size=n)
+        x = host(C.solve(dev(b)))
+        xo = oc.solve(b)
+        assert np.max(np.abs(x - xo)) <= 1e-11 * np.max(np.abs(xo)), rep
+        assert np.max(np.abs(A @ x - b)) <= 1e-12 * np.max(np.abs(b)) * n
+
+
 def _oracle_direction(I):
     g = I.grad(I.x)
     Jm = I.jac(I.x)
