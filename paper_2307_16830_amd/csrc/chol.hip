@@ -53,7 +53,9 @@ struct chol_sym {
     // blocked steps: per (level, step) ranges into the three item lists
     struct Step {
         int level;
-        int32_t p0, p1, t0, t1, s0, s1;
+        int32_t p0, p1, t0, t1;
+        int32_t s0, s1;  // trailing-update tiles of the next panel's 64 columns
+        int32_t r0, r1;  // trailing-update tiles of the columns after it
     };
     std::vector<Step> steps;
     std::vector<int32_t> lvl_step_ptr;
@@ -70,8 +72,12 @@ struct chol_sym {
     DBuf<int32_t> tile_k, tile_kpos;
     DBuf<int32_t> lvl_sn_d, lvl_small_d, lvl_narrow_d, lvl_wide_d;
     DBuf<int32_t> potrf_it, trsm_it, syrk_it;  // packed items
+    // look-ahead: the trailing update past the next panel runs on a second stream
+    hipStream_t st2 = nullptr;
+    std::vector<hipEvent_t> ev_la;
     DBuf<int32_t> status;
     DBuf<double> fronts, upd, work, ybuf;
+    DBuf<double> ldiag, rdiag;  // compact diagonal blocks and reciprocal pivots of one blocked step
     // sync-free solves of wide fronts: one ready flag per 64-block, compared with a per-sweep epoch
     std::vector<int64_t> h_flag_off;  // per supernode (wide fronts only)
     DBuf<int32_t> sflags, sfault;
@@ -88,6 +94,8 @@ struct chol_sym {
     std::vector<double> step_syrk_flops;  // algorithmic flops of each blocked step's trailing update
     ~chol_sym() {
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+        for (hipEvent_t e : ev_la) (void)hipEventDestroy(e);
+        if (st2) (void)hipStreamDestroy(st2);
     }
 };
 
@@ -233,7 +241,7 @@ __device__ __forceinline__ double lane_value(double v, int l) {
 // is a run of independent FMAs with no LDS round trip.  Rows >= kb are zero on entry and stay zero,
 // which makes the inner loop safe to run over the full tile width; entries above the diagonal are
 // updated too (never stored).  Returns the local index of the first rejected pivot or -1.
-__device__ __forceinline__ int wave_potrf(double (&a)[TB], int kb, int lane, double thr) {
+__device__ __forceinline__ int wave_potrf(double (&a)[TB], int kb, int lane, double thr, double& rinv) {
     int bad = -1;
 #pragma unroll
     for (int k = 0; k < TB; k++) {
@@ -245,6 +253,7 @@ __device__ __forceinline__ int wave_potrf(double (&a)[TB], int kb, int lane, dou
             }
             const double r = sqrt(d);
             const double lik = lane == k ? r : a[k] / r;
+            if (lane == k) rinv = 1.0 / r;
             a[k] = lik;
 #pragma unroll
             for (int j = k + 1; j < TB; j++) a[j] -= lik * lane_value(lik, j);
@@ -253,10 +262,14 @@ __device__ __forceinline__ int wave_potrf(double (&a)[TB], int kb, int lane, dou
     return bad;
 }
 
-// Cholesky of the diagonal block of one blocked step (one wave per front).
+// Cholesky of the diagonal block of one blocked step (one wave per front).  Besides writing L_D into
+// the front, it leaves a compact copy for the panel solve in slot blockIdx.x of ldiag (64 x 64,
+// column-major, a partial block padded with the identity) and the reciprocals of its pivots in rdiag
+// (padded with ones).
 __global__ __launch_bounds__(64) void blk_potrf(const int32_t* __restrict__ it, const int32_t* __restrict__ first,
                                                 const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
                                                 const int64_t* __restrict__ foff, double* __restrict__ fronts,
+                                                double* __restrict__ ldiag, double* __restrict__ rdiag,
                                                 int32_t* __restrict__ status, PivotRef pr) {
     const int s = it[2 * blockIdx.x], k0 = it[2 * blockIdx.x + 1];
     const int m = mrows[s];
@@ -268,49 +281,69 @@ __global__ __launch_bounds__(64) void blk_potrf(const int32_t* __restrict__ it, 
     double a[TB];
 #pragma unroll
     for (int j = 0; j < TB; j++) a[j] = (j < kb && lane < kb && j <= lane) ? F[lane + (int64_t)m * j] : 0.0;
-    const int bad = wave_potrf(a, kb, lane, thr);
+    double rinv = 1.0;
+    const int bad = wave_potrf(a, kb, lane, thr, rinv);
 #pragma unroll
     for (int j = 0; j < TB; j++)
         if (j < kb && lane < kb && j <= lane) F[lane + (int64_t)m * j] = a[j];
+    double* Lc = ldiag + (int64_t)blockIdx.x * TB * TB + lane;
+#pragma unroll
+    for (int j = 0; j < TB; j++) Lc[TB * j] = (j < kb && lane < kb) ? (j <= lane ? a[j] : 0.0) : (j == lane ? 1.0 : 0.0);
+    rdiag[(int64_t)blockIdx.x * TB + lane] = lane < kb ? rinv : 1.0;
     if (lane == 0 && bad >= 0) status[s] = min(status[s], p0 + bad);
 }
 
-// X <- X L_D^{-T} below the diagonal block: one thread per panel row (256 rows per work-group) with
-// the row in registers, L_D staged in LDS and read as broadcasts; two accumulators per inner product.
-__global__ __launch_bounds__(NT) void blk_trsm(const int32_t* __restrict__ it, const int32_t* __restrict__ ncol,
+// X <- X L_D^{-T} below the diagonal block: one thread per panel row, 64 rows per work-group, the row in
+// registers.  L_D and its reciprocal pivots come from the compact copy left by the diagonal-block
+// kernel (slot = item field 3); they are read-only here and addressed uniformly with fixed offsets, so
+// they are fetched through the scalar unit into scalar registers and feed the FMAs directly (no LDS).
+// The identity padding of a partial block lets the fully unrolled substitution run without guards;
+// the columns past kb are never stored.
+constexpr int TR = 64;  // panel rows per work-group
+
+__global__ __launch_bounds__(TR) void blk_trsm(const int32_t* __restrict__ it, const int32_t* __restrict__ ncol,
                                                const int32_t* __restrict__ mrows, const int64_t* __restrict__ foff,
+                                               const double* __restrict__ ldiag, const double* __restrict__ rdiag,
                                                double* __restrict__ fronts) {
-    __shared__ double Ld[TB * (TB + 1)];
-    const int s = it[3 * blockIdx.x], k0 = it[3 * blockIdx.x + 1], rb = it[3 * blockIdx.x + 2];
+    const int s = it[4 * blockIdx.x], k0 = it[4 * blockIdx.x + 1], rb = it[4 * blockIdx.x + 2];
+    const int slot = it[4 * blockIdx.x + 3];
     const int m = mrows[s];
     const int kb = min(TB, ncol[s] - k0);
-    double* F = fronts + foff[s];
-    for (int e = threadIdx.x; e < kb * kb; e += NT) {
-        const int r = e % kb, c = e / kb;
-        if (r >= c) Ld[r * (TB + 1) + c] = F[(int64_t)(k0 + r) + (int64_t)m * (k0 + c)];
+    const int last = kb - 1;
+    const double* Lc = ldiag + (int64_t)slot * TB * TB;
+    const double* rc = rdiag + (int64_t)slot * TB;
+    // The compact block was just written from one compute unit; pull it into this die's L2 with a few
+    // wide vector loads so that the scalar loads below hit there instead of going to memory one by one.
+    {
+        const double2* L2v = reinterpret_cast<const double2*>(Lc);
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+            double2 v[8];
+#pragma unroll
+            for (int c = 0; c < 8; c++) v[c] = L2v[(b * 8 + c) * TR + threadIdx.x];
+#pragma unroll
+            for (int c = 0; c < 8; c++) asm volatile("" ::"v"(v[c].x), "v"(v[c].y));
+        }
+        const double r = rc[threadIdx.x];
+        asm volatile("" ::"v"(r));
     }
-    __syncthreads();
-    const int row = k0 + kb + rb * NT + threadIdx.x;
+    const int row = k0 + kb + rb * TR + threadIdx.x;
     if (row >= m) return;
+    double* X = fronts + foff[s] + row + (int64_t)m * k0;  // X[m j] = entry (row, k0 + j)
+    // column indices clamped to the last valid column keep the code free of branches (uniform guards
+    // here make the compiler hoist the scalar loads and spill them); the stores run last column
+    // first, so the clamped duplicates are overwritten by the valid value.
     double x[TB];
 #pragma unroll
-    for (int j = 0; j < TB; j++) x[j] = j < kb ? F[(int64_t)row + (int64_t)m * (k0 + j)] : 0.0;
+    for (int j = 0; j < TB; j++) x[j] = X[(int64_t)m * min(j, last)];
 #pragma unroll
     for (int j = 0; j < TB; j++) {
-        if (j < kb) {
-            double acc0 = x[j], acc1 = 0.0;
+        x[j] *= rc[j];
 #pragma unroll
-            for (int t = 0; t + 1 < j; t += 2) {
-                acc0 -= x[t] * Ld[j * (TB + 1) + t];
-                acc1 -= x[t + 1] * Ld[j * (TB + 1) + t + 1];
-            }
-            if (j & 1) acc0 -= x[j - 1] * Ld[j * (TB + 1) + j - 1];
-            x[j] = (acc0 + acc1) / Ld[j * (TB + 1) + j];
-        }
+        for (int t = j + 1; t < TB; t++) x[t] -= x[j] * Lc[t + TB * j];
     }
 #pragma unroll
-    for (int j = 0; j < TB; j++)
-        if (j < kb) F[(int64_t)row + (int64_t)m * (k0 + j)] = x[j];
+    for (int j = TB - 1; j >= 0; j--) X[(int64_t)m * min(j, last)] = x[j];
 }
 
 // C(bi, bj) -= P_bi P_bj^T on the trailing matrix, 128 x 128 tiles, FP64 MFMA 16x16x4.
@@ -319,24 +352,23 @@ __global__ __launch_bounds__(NT) void blk_trsm(const int32_t* __restrict__ it, c
 typedef double double4_t __attribute__((ext_vector_type(4)));
 constexpr int KC = 16;
 
+// Item: (front, k0, first row ri0, first column rj0) of a tile of up to 128 rows and cw columns.
 __global__ __launch_bounds__(NT) void blk_syrk(const int32_t* __restrict__ it, const int32_t* __restrict__ ncol,
                                                const int32_t* __restrict__ mrows, const int64_t* __restrict__ foff,
-                                               double* __restrict__ fronts) {
+                                               double* __restrict__ fronts, int cw) {
     __shared__ double Pi[KC][ST + 1];
     __shared__ double Pj[KC][ST + 1];
     const int s = it[4 * blockIdx.x], k0 = it[4 * blockIdx.x + 1];
-    const int bi = it[4 * blockIdx.x + 2], bj = it[4 * blockIdx.x + 3];
+    const int ri0 = it[4 * blockIdx.x + 2], rj0 = it[4 * blockIdx.x + 3];
     const int m = mrows[s];
     const int kb = min(TB, ncol[s] - k0);
-    const int base = k0 + kb;
-    const int ri0 = base + bi * ST, rj0 = base + bj * ST;
-    const int nri = min(ST, m - ri0), nrj = min(ST, m - rj0);
+    const int nri = min(ST, m - ri0), nrj = min(cw, m - rj0);
     const double* F = fronts + foff[s];
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int qr = (wave / 2) * 64, qc = (wave % 2) * 64;
     const int li = lane % 16, lk = lane / 16;
-    // skip the strictly-upper quadrant of a diagonal tile
-    const bool active = !(bi == bj && qc > qr);
+    // skip quadrants outside the tile's columns or strictly above the diagonal
+    const bool active = qc < nrj && ri0 + qr + 63 >= rj0 + qc;
     double4_t acc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; a++)
@@ -857,6 +889,7 @@ static void build_numeric_plan(chol_sym* C, const std::vector<int32_t>& colptr, 
     }
     // blocked-path work lists per level and step for fronts with m > 64
     std::vector<int32_t> pot, trs, syr;
+    int max_slots = 0;
     C->steps.clear();
     C->lvl_step_ptr.assign(nl + 1, 0);
     for (int l = 0; l < nl; l++) {
@@ -866,7 +899,7 @@ static void build_numeric_plan(chol_sym* C, const std::vector<int32_t>& colptr, 
             if (C->h_mrows[s] > TB) maxsteps = std::max(maxsteps, (C->h_ncol[s] + TB - 1) / TB);
         }
         for (int k = 0; k < maxsteps; k++) {
-            chol_sym::Step st{l, (int32_t)pot.size() / 2, 0, (int32_t)trs.size() / 3, 0, (int32_t)syr.size() / 4, 0};
+            chol_sym::Step st{l, (int32_t)pot.size() / 2, 0, (int32_t)trs.size() / 4, 0, 0, 0, 0, 0};
             for (int q = C->lvl_ptr[l]; q < C->lvl_ptr[l + 1]; q++) {
                 int s = C->lvl_sn[q];
                 int m = C->h_mrows[s], nn = C->h_ncol[s];
@@ -874,27 +907,49 @@ static void build_numeric_plan(chol_sym* C, const std::vector<int32_t>& colptr, 
                 int k0 = k * TB;
                 if (k0 >= nn) continue;
                 int kb = std::min(TB, nn - k0);
+                const int slot = (int)pot.size() / 2 - st.p0;  // this item's diagonal-block slot in the step
                 pot.push_back(s);
                 pot.push_back(k0);
                 int rest = m - k0 - kb;
-                int Tr = (rest + NT - 1) / NT;
+                int Tr = (rest + TR - 1) / TR;
                 for (int rb = 0; rb < Tr; rb++) {
                     trs.push_back(s);
                     trs.push_back(k0);
                     trs.push_back(rb);
+                    trs.push_back(slot);
                 }
-                int T = (rest + ST - 1) / ST;
-                for (int bj = 0; bj < T; bj++)
-                    for (int bi = bj; bi < T; bi++) {
-                        syr.push_back(s);
-                        syr.push_back(k0);
-                        syr.push_back(bi);
-                        syr.push_back(bj);
-                    }
             }
             st.p1 = (int32_t)pot.size() / 2;
-            st.t1 = (int32_t)trs.size() / 3;
-            st.s1 = (int32_t)syr.size() / 4;
+            st.t1 = (int32_t)trs.size() / 4;
+            max_slots = std::max(max_slots, st.p1 - st.p0);
+            // trailing update: the next panel's 64 columns (128 x 64 tiles), then the rest (128 x 128)
+            for (int pass = 0; pass < 2; pass++) {
+                if (pass == 0)
+                    st.s0 = (int32_t)syr.size() / 4;
+                else
+                    st.r0 = (int32_t)syr.size() / 4;
+                for (int q = C->lvl_ptr[l]; q < C->lvl_ptr[l + 1]; q++) {
+                    int s = C->lvl_sn[q];
+                    int m = C->h_mrows[s], nn = C->h_ncol[s];
+                    int k0 = k * TB;
+                    if (m <= TB || k0 >= nn) continue;
+                    int base = k0 + std::min(TB, nn - k0);
+                    int c0 = pass == 0 ? base : base + TB;
+                    int c1 = pass == 0 ? std::min(base + TB, m) : m;
+                    int cw = pass == 0 ? TB : ST;
+                    for (int rj0 = c0; rj0 < c1; rj0 += cw)
+                        for (int ri0 = rj0; ri0 < m; ri0 += ST) {
+                            syr.push_back(s);
+                            syr.push_back(k0);
+                            syr.push_back(ri0);
+                            syr.push_back(rj0);
+                        }
+                }
+                if (pass == 0)
+                    st.s1 = (int32_t)syr.size() / 4;
+                else
+                    st.r1 = (int32_t)syr.size() / 4;
+            }
             double fl = 0;
             for (int q = C->lvl_ptr[l]; q < C->lvl_ptr[l + 1]; q++) {
                 int s = C->lvl_sn[q];
@@ -943,6 +998,8 @@ static void build_numeric_plan(chol_sym* C, const std::vector<int32_t>& colptr, 
     C->dev.alloc(C->upd, std::max<int64_t>(uo, 1));
     C->dev.alloc(C->work, std::max<int64_t>(C->h_roff[ns], 1));
     C->dev.alloc(C->ybuf, std::max(n, 1));
+    C->dev.alloc(C->ldiag, (int64_t)std::max(max_slots, 1) * TB * TB);
+    C->dev.alloc(C->rdiag, (int64_t)std::max(max_slots, 1) * TB);
     C->h_flag_off.assign(ns, -1);
     int64_t nflags = 0;
     for (int s = 0; s < ns; s++)
@@ -1074,6 +1131,14 @@ static void tcollect(chol_sym* C) {
 
 void chol_factor_enqueue(chol_sym* C, const double* kval, hipStream_t st, double pivot_tol) {
     C->dev.run();
+    if (!C->st2) {
+        OPF_HIP(hipStreamCreateWithFlags(&C->st2, hipStreamNonBlocking));
+        size_t need = 0;
+        for (int l = 0; l < C->nlevels; l++)
+            need = std::max<size_t>(need, 2 * (size_t)(C->lvl_step_ptr[l + 1] - C->lvl_step_ptr[l]));
+        C->ev_la.resize(need, nullptr);
+        for (auto& e : C->ev_la) OPF_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
     const PivotRef pr{kval, C->kdiagpos.p, pivot_tol};
     for (int l = 0; l < C->nlevels; l++) {
         int t0 = C->asm_ptr[l], t1 = C->asm_ptr[l + 1];
@@ -1093,31 +1158,48 @@ void chol_factor_enqueue(chol_sym* C, const double* kval, hipStream_t st, double
             OPF_LAUNCH_CHECK();
             tmark(C, st, 1);
         }
-        for (int q = C->lvl_step_ptr[l]; q < C->lvl_step_ptr[l + 1]; q++) {
+        const int q0 = C->lvl_step_ptr[l], q1 = C->lvl_step_ptr[l + 1];
+        for (int q = q0; q < q1; q++) {
             const chol_sym::Step& S = C->steps[q];
+            hipEvent_t ev_panel = C->ev_la[2 * (q - q0)], ev_rest = C->ev_la[2 * (q - q0) + 1];
             if (S.p1 > S.p0) {
                 tmark(C, st, 2);
                 hipLaunchKernelGGL(blk_potrf, dim3(S.p1 - S.p0), dim3(64), 0, st, C->potrf_it.p + 2 * S.p0,
-                                   C->first.p, C->ncol.p, C->mrows.p, C->foff.p, C->fronts.p, C->status.p, pr);
+                                   C->first.p, C->ncol.p, C->mrows.p, C->foff.p, C->fronts.p, C->ldiag.p,
+                                   C->rdiag.p, C->status.p, pr);
                 OPF_LAUNCH_CHECK();
                 tmark(C, st, 2);
             }
             if (S.t1 > S.t0) {
                 tmark(C, st, 3);
-                hipLaunchKernelGGL(blk_trsm, dim3(S.t1 - S.t0), dim3(NT), 0, st, C->trsm_it.p + 3 * S.t0, C->ncol.p,
-                                   C->mrows.p, C->foff.p, C->fronts.p);
+                hipLaunchKernelGGL(blk_trsm, dim3(S.t1 - S.t0), dim3(TR), 0, st, C->trsm_it.p + 4 * S.t0, C->ncol.p,
+                                   C->mrows.p, C->foff.p, C->ldiag.p, C->rdiag.p, C->fronts.p);
                 OPF_LAUNCH_CHECK();
                 tmark(C, st, 3);
             }
+            OPF_HIP(hipEventRecord(ev_panel, st));
+            // the previous step's update of the later columns also covers this step's next panel
+            if (q > q0) OPF_HIP(hipStreamWaitEvent(st, C->ev_la[2 * (q - q0) - 1], 0));
             if (S.s1 > S.s0) {
                 tmark(C, st, 4);
                 hipLaunchKernelGGL(blk_syrk, dim3(S.s1 - S.s0), dim3(NT), 0, st, C->syrk_it.p + 4 * S.s0, C->ncol.p,
-                                   C->mrows.p, C->foff.p, C->fronts.p);
+                                   C->mrows.p, C->foff.p, C->fronts.p, TB);
                 OPF_LAUNCH_CHECK();
                 tmark(C, st, 4);
-                if (C->timing) C->t_flops[4] += C->step_syrk_flops[q];
             }
+            OPF_HIP(hipStreamWaitEvent(C->st2, ev_panel, 0));
+            if (S.r1 > S.r0) {
+                tmark(C, C->st2, 4);
+                hipLaunchKernelGGL(blk_syrk, dim3(S.r1 - S.r0), dim3(NT), 0, C->st2, C->syrk_it.p + 4 * S.r0,
+                                   C->ncol.p, C->mrows.p, C->foff.p, C->fronts.p, ST);
+                OPF_LAUNCH_CHECK();
+                tmark(C, C->st2, 4);
+            }
+            OPF_HIP(hipEventRecord(ev_rest, C->st2));
+            if (C->timing) C->t_flops[4] += C->step_syrk_flops[q];
         }
+        // the next level assembles from this level's update matrices
+        if (q1 > q0) OPF_HIP(hipStreamWaitEvent(st, C->ev_la[2 * (q1 - q0) - 1], 0));
     }
 }
 
