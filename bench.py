@@ -87,14 +87,20 @@ def main():
 
     run(args.warmup)
     torch.cuda.synchronize()
-    C.timing(True)  # HIP events around every factorization launch of the timed region
+    # HIP events around each launch of the dominant kernel (the trailing MFMA update) in the timed region
+    C.timing(["trailing_update"])
     t0 = time.perf_counter()
     run(args.steps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     kt = C.timing_read()
+    timed = infos[args.warmup:args.warmup + args.steps]
+    # diagnostic (outside the timed region): every factorization kernel category over two more iterations
+    C.timing(True)
+    run(2)
+    torch.cuda.synchronize()
+    kt_all = C.timing_read()
     C.timing(False)
-    timed = infos[args.warmup:]
     ms = 1e3 * elapsed / args.steps
     fac_ms = np.mean([i["t_factor"] / max(i["factorizations"], 1) for i in timed])
     stage = {k: float(np.mean([i[k] for i in timed])) for k in ("t_ad", "t_assembly", "t_factor", "t_solve")}
@@ -106,8 +112,8 @@ def main():
     avg_ms = tu["ms"] / max(tu["launches"], 1)
     flops_per_launch = tu["flops"] / max(tu["launches"], 1)
     achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
-    log(f"[bench] factorization kernels over the timed region: " +
-        ", ".join(f"{k} {v['ms']:.2f} ms/{v['launches']} launches" for k, v in kt.items()))
+    log(f"[bench] factorization kernels per iteration (diagnostic pass): " +
+        ", ".join(f"{k} {v['ms'] / 2:.2f} ms/{v['launches'] // 2} launches" for k, v in kt_all.items()))
     out = {
         "metric": "ACOPF IPM iter/s at 10k buses",
         "value": args.steps / elapsed,
@@ -132,7 +138,7 @@ def main():
                      "avg_launch_ms": avg_ms, "flops_per_launch": flops_per_launch,
                      "launches": tu["launches"]},
         "factorization_tflops": factor_tflops,
-        "factor_kernels_ms": {k: v["ms"] for k, v in kt.items()},
+        "factor_kernels_ms_per_iter": {k: v["ms"] / 2 for k, v in kt_all.items()},
     }
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on one iteration of the same grid")

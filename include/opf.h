@@ -173,16 +173,21 @@ int chol_supernode_rows(const chol_sym* sym, int64_t* rows_ptr, int32_t* rows);
  * HBM. */
 int chol_factor(chol_sym* sym, const double* kval, void* stream, int32_t* bad_col);
 /* x = K^{-1} b using the last successful factor; b, x device [n*nrhs]
- * (column-major, leading dimension n; x may alias b).  Asynchronous. */
+ * (column-major, leading dimension n; x may alias b).  Returns after the
+ * solve has run on `stream`: fronts with many pivots are solved by
+ * work-groups that wait on each other's ready flags with a bounded spin, and
+ * a wait that ran out (never expected) is reported as OPF_E_DEVICE. */
 int chol_solve(chol_sym* sym, const double* b, double* x, int32_t nrhs, void* stream);
-/* Kernel timing of the numeric factorizations (measurement aid).  With
- * timing enabled, every factorization launch is bracketed by HIP events on
- * its stream; chol_timing_read returns, for the categories [assembly,
- * small fronts, diagonal-block Cholesky, panel solve, trailing MFMA update],
- * the summed kernel milliseconds ms[5], the launch counts launches[5] and the
- * algorithmic flops flops[5] (filled for the trailing update: the symmetric
- * rank-64 updates of each step's lower triangle).  Enabling resets them. */
-int chol_timing(chol_sym* sym, int enable);
+/* Kernel timing of the numeric factorizations (measurement aid).  `mask`
+ * selects categories by bit: 1 assembly, 2 small fronts, 4 diagonal-block
+ * Cholesky, 8 panel solve, 16 trailing MFMA update (0 disables).  Every
+ * launch of a selected category is bracketed by HIP events on the stream it
+ * runs on (the events themselves add a little latency between launches);
+ * chol_timing_read returns, per category, the summed kernel milliseconds
+ * ms[5], the launch counts launches[5] and the algorithmic flops flops[5]
+ * (filled for the trailing update: the symmetric rank-64 updates of each
+ * step's lower triangle).  Calling chol_timing resets them. */
+int chol_timing(chol_sym* sym, int mask);
 int chol_timing_read(const chol_sym* sym, double* ms, int64_t* launches, double* flops);
 /* Copy L to the host as CSC in pivot order over the supernodal pattern
  * (lp [n+1], li [nnz_l], lx [nnz_l]); explicit zeros included. */

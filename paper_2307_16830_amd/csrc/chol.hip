@@ -83,8 +83,8 @@ struct chol_sym {
     DBuf<int32_t> sflags, sfault;
     int32_t epoch = 0;
     Deferred dev;  // pending uploads, run at the first device use
-    // optional per-category kernel timing (assemble, small, potrf, trsm, syrk)
-    bool timing = false;
+    // optional per-category kernel timing (assemble, small, potrf, trsm, syrk): bit mask of categories
+    int timing = 0;
     std::vector<hipEvent_t> ev_pool;
     std::vector<int> ev_cat;
     size_t ev_used = 0;
@@ -351,76 +351,90 @@ __global__ __launch_bounds__(TR) void blk_trsm(const int32_t* __restrict__ it, c
 // the panel rows are staged through LDS in chunks of 16 columns.
 typedef double double4_t __attribute__((ext_vector_type(4)));
 constexpr int KC = 16;
+constexpr int REST_GRID = 224;  // work-groups of the off-critical-path update (of 256 compute units)
 
-// Item: (front, k0, first row ri0, first column rj0) of a tile of up to 128 rows and cw columns.
-__global__ __launch_bounds__(NT) void blk_syrk(const int32_t* __restrict__ it, const int32_t* __restrict__ ncol,
-                                               const int32_t* __restrict__ mrows, const int64_t* __restrict__ foff,
-                                               double* __restrict__ fronts, int cw) {
+// Item: (front, k0, first row ri0, first column rj0) of a tile of up to 128 rows and cw columns.  The
+// grid may be smaller than the item count (work-groups loop over items), which leaves compute units
+// free for the launches of the critical path running beside it.  The accumulators start from the
+// tile of C and the row panel is negated on its way into LDS, so the MFMAs accumulate C - Pi Pj^T and
+// the tile is read once, at the start, where its latency overlaps the first panel loads.
+__global__ __launch_bounds__(NT) void blk_syrk(const int32_t* __restrict__ it, int nitems,
+                                               const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
+                                               const int64_t* __restrict__ foff, double* __restrict__ fronts,
+                                               int cw) {
     __shared__ double Pi[KC][ST + 1];
     __shared__ double Pj[KC][ST + 1];
-    const int s = it[4 * blockIdx.x], k0 = it[4 * blockIdx.x + 1];
-    const int ri0 = it[4 * blockIdx.x + 2], rj0 = it[4 * blockIdx.x + 3];
-    const int m = mrows[s];
-    const int kb = min(TB, ncol[s] - k0);
-    const int nri = min(ST, m - ri0), nrj = min(cw, m - rj0);
-    const double* F = fronts + foff[s];
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int qr = (wave / 2) * 64, qc = (wave % 2) * 64;
     const int li = lane % 16, lk = lane / 16;
-    // skip quadrants outside the tile's columns or strictly above the diagonal
-    const bool active = qc < nrj && ri0 + qr + 63 >= rj0 + qc;
-    double4_t acc[4][4];
+    for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+        const int s = it[4 * item], k0 = it[4 * item + 1];
+        const int ri0 = it[4 * item + 2], rj0 = it[4 * item + 3];
+        const int m = mrows[s];
+        const int kb = min(TB, ncol[s] - k0);
+        const int nri = min(ST, m - ri0), nrj = min(cw, m - rj0);
+        double* F = fronts + foff[s];
+        // quadrants outside the tile's columns or strictly above the diagonal do no MFMA work
+        const bool active = qc < nrj && ri0 + qr + 63 >= rj0 + qc;
+        // D layout of the 16x16x4 f64 MFMA: item r of a lane is row (lane / 16) + 4 r, column lane % 16
+        // of the product block; operands are swapped below so the block is C^T: C row = lane % 16,
+        // C column = (lane / 16) + 4 r (16 consecutive rows of a column per 16-lane group)
+        double4_t acc[4][4];
 #pragma unroll
-    for (int a = 0; a < 4; a++)
+        for (int a = 0; a < 4; a++)
 #pragma unroll
-        for (int b = 0; b < 4; b++) acc[a][b] = double4_t{0.0, 0.0, 0.0, 0.0};
-    for (int t0 = 0; t0 < kb; t0 += KC) {
-        __syncthreads();
-        for (int e = threadIdx.x; e < ST * KC; e += NT) {
-            const int r = e % ST, t = e / ST;
-            const int tt = t0 + t;
-            double a = 0.0, b = 0.0;
-            if (tt < kb) {
-                if (r < nri) a = F[(int64_t)(ri0 + r) + (int64_t)m * (k0 + tt)];
-                if (r < nrj) b = F[(int64_t)(rj0 + r) + (int64_t)m * (k0 + tt)];
+            for (int b = 0; b < 4; b++)
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const int i = qr + 16 * a + li;
+                    const int j = qc + 16 * b + lk + 4 * r;
+                    const int gi = ri0 + i, gj = rj0 + j;
+                    acc[a][b][r] = (active && i < nri && j < nrj && gi >= gj) ? F[(int64_t)gi + (int64_t)m * gj] : 0.0;
+                }
+        for (int t0 = 0; t0 < kb; t0 += KC) {
+            __syncthreads();
+            for (int e = threadIdx.x; e < ST * KC; e += NT) {
+                const int r = e % ST, t = e / ST;
+                const int tt = t0 + t;
+                double a = 0.0, b = 0.0;
+                if (tt < kb) {
+                    if (r < nri) a = F[(int64_t)(ri0 + r) + (int64_t)m * (k0 + tt)];
+                    if (r < nrj) b = F[(int64_t)(rj0 + r) + (int64_t)m * (k0 + tt)];
+                }
+                Pi[t][r] = -a;
+                Pj[t][r] = b;
             }
-            Pi[t][r] = a;
-            Pj[t][r] = b;
+            __syncthreads();
+            if (active) {
+#pragma unroll
+                for (int t = 0; t < KC; t += 4) {
+                    double av[4], bv[4];
+#pragma unroll
+                    for (int a = 0; a < 4; a++) av[a] = Pi[t + lk][qr + 16 * a + li];
+#pragma unroll
+                    for (int b = 0; b < 4; b++) bv[b] = Pj[t + lk][qc + 16 * b + li];
+#pragma unroll
+                    for (int a = 0; a < 4; a++)
+#pragma unroll
+                        for (int b = 0; b < 4; b++)
+                            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[b], av[a], acc[a][b], 0, 0, 0);
+                }
+            }
         }
-        __syncthreads();
         if (active) {
 #pragma unroll
-            for (int t = 0; t < KC; t += 4) {
-                double av[4], bv[4];
+            for (int a = 0; a < 4; a++)
 #pragma unroll
-                for (int a = 0; a < 4; a++) av[a] = Pi[t + lk][qr + 16 * a + li];
+                for (int b = 0; b < 4; b++)
 #pragma unroll
-                for (int b = 0; b < 4; b++) bv[b] = Pj[t + lk][qc + 16 * b + li];
-                // operands swapped: the product block is C^T, so a 16-lane group holds 16 consecutive
-                // rows of one column of C (coalesced column-major writes)
-#pragma unroll
-                for (int a = 0; a < 4; a++)
-#pragma unroll
-                    for (int b = 0; b < 4; b++)
-                        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[b], av[a], acc[a][b], 0, 0, 0);
-            }
+                    for (int r = 0; r < 4; r++) {
+                        const int i = qr + 16 * a + li;
+                        const int j = qc + 16 * b + lk + 4 * r;
+                        const int gi = ri0 + i, gj = rj0 + j;
+                        if (i < nri && j < nrj && gi >= gj) F[(int64_t)gi + (int64_t)m * gj] = acc[a][b][r];
+                    }
         }
     }
-    if (!active) return;
-    double* Fw = fronts + foff[s];
-    // D layout of the 16x16x4 f64 MFMA: item r of a lane is row (lane / 16) + 4 r, column lane % 16 of
-    // the product block, here C^T: C row = lane % 16, C column = (lane / 16) + 4 r
-#pragma unroll
-    for (int a = 0; a < 4; a++)
-#pragma unroll
-        for (int b = 0; b < 4; b++)
-#pragma unroll
-            for (int r = 0; r < 4; r++) {
-                const int i = qr + 16 * a + (lane % 16);
-                const int j = qc + 16 * b + (lane / 16) + 4 * r;
-                const int gi = ri0 + i, gj = rj0 + j;
-                if (i < nri && j < nrj && gi >= gj) Fw[(int64_t)gi + (int64_t)m * gj] -= acc[a][b][r];
-            }
 }
 
 // ---------------------------------------------------------------- solves
@@ -1106,7 +1120,7 @@ namespace opf {
 
 // Enqueue the numeric factorization (no synchronisation).
 static void tmark(chol_sym* C, hipStream_t st, int cat) {
-    if (!C->timing) return;
+    if (!(C->timing & (1 << cat))) return;
     if (C->ev_used == C->ev_pool.size()) {
         hipEvent_t e;
         OPF_HIP(hipEventCreate(&e));
@@ -1182,21 +1196,22 @@ void chol_factor_enqueue(chol_sym* C, const double* kval, hipStream_t st, double
             if (q > q0) OPF_HIP(hipStreamWaitEvent(st, C->ev_la[2 * (q - q0) - 1], 0));
             if (S.s1 > S.s0) {
                 tmark(C, st, 4);
-                hipLaunchKernelGGL(blk_syrk, dim3(S.s1 - S.s0), dim3(NT), 0, st, C->syrk_it.p + 4 * S.s0, C->ncol.p,
-                                   C->mrows.p, C->foff.p, C->fronts.p, TB);
+                hipLaunchKernelGGL(blk_syrk, dim3(S.s1 - S.s0), dim3(NT), 0, st, C->syrk_it.p + 4 * S.s0, S.s1 - S.s0,
+                                   C->ncol.p, C->mrows.p, C->foff.p, C->fronts.p, TB);
                 OPF_LAUNCH_CHECK();
                 tmark(C, st, 4);
             }
             OPF_HIP(hipStreamWaitEvent(C->st2, ev_panel, 0));
             if (S.r1 > S.r0) {
                 tmark(C, C->st2, 4);
-                hipLaunchKernelGGL(blk_syrk, dim3(S.r1 - S.r0), dim3(NT), 0, C->st2, C->syrk_it.p + 4 * S.r0,
-                                   C->ncol.p, C->mrows.p, C->foff.p, C->fronts.p, ST);
+                hipLaunchKernelGGL(blk_syrk, dim3(std::min(S.r1 - S.r0, REST_GRID)), dim3(NT), 0, C->st2,
+                                   C->syrk_it.p + 4 * S.r0, S.r1 - S.r0, C->ncol.p, C->mrows.p, C->foff.p,
+                                   C->fronts.p, ST);
                 OPF_LAUNCH_CHECK();
                 tmark(C, C->st2, 4);
             }
             OPF_HIP(hipEventRecord(ev_rest, C->st2));
-            if (C->timing) C->t_flops[4] += C->step_syrk_flops[q];
+            if (C->timing & (1 << 4)) C->t_flops[4] += C->step_syrk_flops[q];
         }
         // the next level assembles from this level's update matrices
         if (q1 > q0) OPF_HIP(hipStreamWaitEvent(st, C->ev_la[2 * (q1 - q0) - 1], 0));
@@ -1357,7 +1372,7 @@ extern "C" int chol_export_factor(chol_sym* C, int64_t* lp, int32_t* li, double*
 extern "C" int chol_timing(chol_sym* C, int enable) {
     return guarded([&] {
         OPF_CHECK(C, OPF_E_INVALID, "chol_timing: null handle");
-        C->timing = enable != 0;
+        C->timing = enable & 31;
         C->ev_used = 0;
         for (int q = 0; q < 5; q++) {
             C->t_ms[q] = 0;

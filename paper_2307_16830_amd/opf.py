@@ -304,8 +304,14 @@ class Cholesky:
 
     TIMING_CATEGORIES = ("assembly", "small_fronts", "diag_block", "panel_solve", "trailing_update")
 
-    def timing(self, enable=True):
-        _check(lib().chol_timing(self._h, int(bool(enable))), "chol_timing")
+    def timing(self, categories=True):
+        """Bracket the launches of the given categories (names from TIMING_CATEGORIES, or a bit mask;
+        empty / 0 disables) with HIP events; resets the totals."""
+        if isinstance(categories, (int, bool)):
+            mask = 31 if categories is True else int(categories)
+        else:
+            mask = sum(1 << self.TIMING_CATEGORIES.index(c) for c in categories)
+        _check(lib().chol_timing(self._h, mask), "chol_timing")
 
     def timing_read(self):
         ms = np.zeros(5)
