@@ -72,6 +72,7 @@ struct chol_sym {
     DBuf<int32_t> tile_k, tile_kpos;
     DBuf<int32_t> lvl_sn_d, lvl_small_d, lvl_narrow_d, lvl_wide_d;
     DBuf<int32_t> potrf_it, trsm_it, syrk_it;  // packed items
+    DBuf<int32_t> next_slot;  // per trailing-update item: slot of the next panel's diagonal block, or -1
     // look-ahead: the trailing update past the next panel runs on a second stream
     hipStream_t st2 = nullptr;
     std::vector<hipEvent_t> ev_la;
@@ -262,20 +263,18 @@ __device__ __forceinline__ int wave_potrf(double (&a)[TB], int kb, int lane, dou
     return bad;
 }
 
-// Cholesky of the diagonal block of one blocked step (one wave per front).  Besides writing L_D into
-// the front, it leaves a compact copy for the panel solve in slot blockIdx.x of ldiag (64 x 64,
+// Cholesky of the diagonal block at (k0, k0) of front s by one wave (lane = row).  Besides writing L_D
+// into the front, it leaves a compact copy for the panel solve in slot `slot` of ldiag (64 x 64,
 // column-major, a partial block padded with the identity) and the reciprocals of its pivots in rdiag
-// (padded with ones).
-__global__ __launch_bounds__(64) void blk_potrf(const int32_t* __restrict__ it, const int32_t* __restrict__ first,
-                                                const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
-                                                const int64_t* __restrict__ foff, double* __restrict__ fronts,
-                                                double* __restrict__ ldiag, double* __restrict__ rdiag,
-                                                int32_t* __restrict__ status, PivotRef pr) {
-    const int s = it[2 * blockIdx.x], k0 = it[2 * blockIdx.x + 1];
+// (padded with ones), and lowers status[s] to the first rejected pivot.
+__device__ __forceinline__ void potrf_block(int s, int k0, int slot, int lane, const int32_t* __restrict__ first,
+                                            const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
+                                            const int64_t* __restrict__ foff, double* __restrict__ fronts,
+                                            double* __restrict__ ldiag, double* __restrict__ rdiag,
+                                            int32_t* __restrict__ status, const PivotRef& pr) {
     const int m = mrows[s];
     const int kb = min(TB, ncol[s] - k0);
     double* F = fronts + foff[s] + (int64_t)k0 + (int64_t)m * k0;
-    const int lane = threadIdx.x;
     const int p0 = first[s] + k0;
     const double thr = lane < kb ? pr.thresh(p0 + lane) : 0.0;
     double a[TB];
@@ -286,11 +285,22 @@ __global__ __launch_bounds__(64) void blk_potrf(const int32_t* __restrict__ it, 
 #pragma unroll
     for (int j = 0; j < TB; j++)
         if (j < kb && lane < kb && j <= lane) F[lane + (int64_t)m * j] = a[j];
-    double* Lc = ldiag + (int64_t)blockIdx.x * TB * TB + lane;
+    double* Lc = ldiag + (int64_t)slot * TB * TB + lane;
 #pragma unroll
     for (int j = 0; j < TB; j++) Lc[TB * j] = (j < kb && lane < kb) ? (j <= lane ? a[j] : 0.0) : (j == lane ? 1.0 : 0.0);
-    rdiag[(int64_t)blockIdx.x * TB + lane] = lane < kb ? rinv : 1.0;
+    rdiag[(int64_t)slot * TB + lane] = lane < kb ? rinv : 1.0;
     if (lane == 0 && bad >= 0) status[s] = min(status[s], p0 + bad);
+}
+
+// Diagonal blocks of the first blocked step of each front (later steps factor theirs inside the
+// trailing update of the step before, see blk_syrk).
+__global__ __launch_bounds__(64) void blk_potrf(const int32_t* __restrict__ it, const int32_t* __restrict__ first,
+                                                const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
+                                                const int64_t* __restrict__ foff, double* __restrict__ fronts,
+                                                double* __restrict__ ldiag, double* __restrict__ rdiag,
+                                                int32_t* __restrict__ status, PivotRef pr) {
+    potrf_block(it[2 * blockIdx.x], it[2 * blockIdx.x + 1], blockIdx.x, threadIdx.x, first, ncol, mrows, foff,
+                fronts, ldiag, rdiag, status, pr);
 }
 
 // X <- X L_D^{-T} below the diagonal block: one thread per panel row, 64 rows per work-group, the row in
@@ -358,10 +368,16 @@ constexpr int REST_GRID = 224;  // work-groups of the off-critical-path update (
 // free for the launches of the critical path running beside it.  The accumulators start from the
 // tile of C and the row panel is negated on its way into LDS, so the MFMAs accumulate C - Pi Pj^T and
 // the tile is read once, at the start, where its latency overlaps the first panel loads.
+// With pslot given (the update of the next panel's 64 columns), the work-group holding a front's
+// diagonal tile goes on to factor the next panel's diagonal block, which it has just brought up to
+// date, into ldiag slot pslot[item] (-1: no such block); that saves the diagonal-block launch.
 __global__ __launch_bounds__(NT) void blk_syrk(const int32_t* __restrict__ it, int nitems,
                                                const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
                                                const int64_t* __restrict__ foff, double* __restrict__ fronts,
-                                               int cw) {
+                                               int cw, const int32_t* __restrict__ pslot,
+                                               const int32_t* __restrict__ first, double* __restrict__ ldiag,
+                                               double* __restrict__ rdiag, int32_t* __restrict__ status,
+                                               PivotRef pr) {
     __shared__ double Pi[KC][ST + 1];
     __shared__ double Pj[KC][ST + 1];
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
@@ -433,6 +449,11 @@ __global__ __launch_bounds__(NT) void blk_syrk(const int32_t* __restrict__ it, i
                         const int gi = ri0 + i, gj = rj0 + j;
                         if (i < nri && j < nrj && gi >= gj) F[(int64_t)gi + (int64_t)m * gj] = acc[a][b][r];
                     }
+        }
+        if (pslot && pslot[item] >= 0) {
+            __syncthreads();  // the tile's stores are visible to the whole work-group
+            if (wave == 0)
+                potrf_block(s, rj0, pslot[item], lane, first, ncol, mrows, foff, fronts, ldiag, rdiag, status, pr);
         }
     }
 }
@@ -902,7 +923,7 @@ static void build_numeric_plan(chol_sym* C, const std::vector<int32_t>& colptr, 
         }
     }
     // blocked-path work lists per level and step for fronts with m > 64
-    std::vector<int32_t> pot, trs, syr;
+    std::vector<int32_t> pot, trs, syr, nslot;
     int max_slots = 0;
     C->steps.clear();
     C->lvl_step_ptr.assign(nl + 1, 0);
@@ -957,6 +978,17 @@ static void build_numeric_plan(chol_sym* C, const std::vector<int32_t>& colptr, 
                             syr.push_back(k0);
                             syr.push_back(ri0);
                             syr.push_back(rj0);
+                            // the next panel's diagonal tile factors that panel's diagonal block; its slot is
+                            // the front's position among the fronts with a panel at the next step
+                            int ns = -1;
+                            if (pass == 0 && ri0 == base && base < nn) {
+                                ns = 0;
+                                for (int q2 = C->lvl_ptr[l]; q2 < q; q2++) {
+                                    int s2 = C->lvl_sn[q2];
+                                    if (C->h_mrows[s2] > TB && (k + 1) * TB < C->h_ncol[s2]) ns++;
+                                }
+                            }
+                            nslot.push_back(ns);
                         }
                 }
                 if (pass == 0)
@@ -1007,6 +1039,7 @@ static void build_numeric_plan(chol_sym* C, const std::vector<int32_t>& colptr, 
     C->dev.upload(C->potrf_it, pot);
     C->dev.upload(C->trsm_it, trs);
     C->dev.upload(C->syrk_it, syr);
+    C->dev.upload(C->next_slot, nslot);
     C->dev.alloc(C->status, std::max(ns, 1));
     C->dev.alloc(C->fronts, std::max<int64_t>(fo, 1));
     C->dev.alloc(C->upd, std::max<int64_t>(uo, 1));
@@ -1176,7 +1209,7 @@ void chol_factor_enqueue(chol_sym* C, const double* kval, hipStream_t st, double
         for (int q = q0; q < q1; q++) {
             const chol_sym::Step& S = C->steps[q];
             hipEvent_t ev_panel = C->ev_la[2 * (q - q0)], ev_rest = C->ev_la[2 * (q - q0) + 1];
-            if (S.p1 > S.p0) {
+            if (q == q0 && S.p1 > S.p0) {  // later steps factor their diagonal blocks in the update before
                 tmark(C, st, 2);
                 hipLaunchKernelGGL(blk_potrf, dim3(S.p1 - S.p0), dim3(64), 0, st, C->potrf_it.p + 2 * S.p0,
                                    C->first.p, C->ncol.p, C->mrows.p, C->foff.p, C->fronts.p, C->ldiag.p,
@@ -1197,7 +1230,8 @@ void chol_factor_enqueue(chol_sym* C, const double* kval, hipStream_t st, double
             if (S.s1 > S.s0) {
                 tmark(C, st, 4);
                 hipLaunchKernelGGL(blk_syrk, dim3(S.s1 - S.s0), dim3(NT), 0, st, C->syrk_it.p + 4 * S.s0, S.s1 - S.s0,
-                                   C->ncol.p, C->mrows.p, C->foff.p, C->fronts.p, TB);
+                                   C->ncol.p, C->mrows.p, C->foff.p, C->fronts.p, TB, C->next_slot.p + S.s0,
+                                   C->first.p, C->ldiag.p, C->rdiag.p, C->status.p, pr);
                 OPF_LAUNCH_CHECK();
                 tmark(C, st, 4);
             }
@@ -1206,7 +1240,7 @@ void chol_factor_enqueue(chol_sym* C, const double* kval, hipStream_t st, double
                 tmark(C, C->st2, 4);
                 hipLaunchKernelGGL(blk_syrk, dim3(std::min(S.r1 - S.r0, REST_GRID)), dim3(NT), 0, C->st2,
                                    C->syrk_it.p + 4 * S.r0, S.r1 - S.r0, C->ncol.p, C->mrows.p, C->foff.p,
-                                   C->fronts.p, ST);
+                                   C->fronts.p, ST, nullptr, nullptr, nullptr, nullptr, nullptr, pr);
                 OPF_LAUNCH_CHECK();
                 tmark(C, C->st2, 4);
             }
