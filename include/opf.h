@@ -184,11 +184,13 @@ int chol_solve(chol_sym* sym, const double* b, double* x, int32_t nrhs, void* st
  * launch of a selected category is bracketed by HIP events on the stream it
  * runs on (the events themselves add a little latency between launches);
  * chol_timing_read returns, per category, the summed kernel milliseconds
- * ms[5], the launch counts launches[5] and the algorithmic flops flops[5]
- * (filled for the trailing update: the symmetric rank-64 updates of each
- * step's lower triangle).  Calling chol_timing resets them. */
+ * ms[5], the launch counts launches[5], and the algorithmic flops flops[5]
+ * and HBM bytes bytes[5] (filled for the trailing update: the symmetric
+ * rank-64 update of each step's lower triangle; bytes = every updated entry
+ * read and written once plus the panel rows read once per launch).  Any
+ * output pointer may be null.  Calling chol_timing resets them. */
 int chol_timing(chol_sym* sym, int mask);
-int chol_timing_read(const chol_sym* sym, double* ms, int64_t* launches, double* flops);
+int chol_timing_read(const chol_sym* sym, double* ms, int64_t* launches, double* flops, double* bytes);
 /* Copy L to the host as CSC in pivot order over the supernodal pattern
  * (lp [n+1], li [nnz_l], lx [nnz_l]); explicit zeros included. */
 int chol_export_factor(chol_sym* sym, int64_t* lp, int32_t* li, double* lx);

@@ -92,7 +92,9 @@ struct chol_sym {
     double t_ms[5] = {0, 0, 0, 0, 0};
     int64_t t_launch[5] = {0, 0, 0, 0, 0};
     double t_flops[5] = {0, 0, 0, 0, 0};
+    double t_bytes[5] = {0, 0, 0, 0, 0};
     std::vector<double> step_syrk_flops;  // algorithmic flops of each blocked step's trailing update
+    std::vector<double> step_syrk_bytes;  // and its algorithmic HBM bytes (C read + written, panel read once)
     ~chol_sym() {
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
         for (hipEvent_t e : ev_la) (void)hipEventDestroy(e);
@@ -996,15 +998,20 @@ static void build_numeric_plan(chol_sym* C, const std::vector<int32_t>& colptr, 
                 else
                     st.r1 = (int32_t)syr.size() / 4;
             }
-            double fl = 0;
+            double fl = 0, by = 0;
             for (int q = C->lvl_ptr[l]; q < C->lvl_ptr[l + 1]; q++) {
                 int s = C->lvl_sn[q];
                 int m = C->h_mrows[s], nn = C->h_ncol[s];
                 if (m <= TB || k * TB >= nn) continue;
                 double kb = std::min(TB, nn - k * TB), r = m - k * TB - kb;
                 fl += r * (r + 1) * kb;  // symmetric rank-kb update of an r x r lower triangle
+                // both launches of the step: every lower entry of the r x r block read and written once
+                // (16 B); the panel rows read once per launch (the next-panel launch and the rest)
+                const double rest = std::max(0.0, r - TB);
+                by += 16.0 * r * (r + 1) / 2 + 8.0 * kb * (r + rest);
             }
             C->step_syrk_flops.push_back(fl);
+            C->step_syrk_bytes.push_back(by);
             C->steps.push_back(st);
         }
         C->lvl_step_ptr[l + 1] = (int32_t)C->steps.size();
@@ -1245,7 +1252,10 @@ void chol_factor_enqueue(chol_sym* C, const double* kval, hipStream_t st, double
                 tmark(C, C->st2, 4);
             }
             OPF_HIP(hipEventRecord(ev_rest, C->st2));
-            if (C->timing & (1 << 4)) C->t_flops[4] += C->step_syrk_flops[q];
+            if (C->timing & (1 << 4)) {
+                C->t_flops[4] += C->step_syrk_flops[q];
+                C->t_bytes[4] += C->step_syrk_bytes[q];
+            }
         }
         // the next level assembles from this level's update matrices
         if (q1 > q0) OPF_HIP(hipStreamWaitEvent(st, C->ev_la[2 * (q1 - q0) - 1], 0));
@@ -1412,17 +1422,19 @@ extern "C" int chol_timing(chol_sym* C, int enable) {
             C->t_ms[q] = 0;
             C->t_launch[q] = 0;
             C->t_flops[q] = 0;
+            C->t_bytes[q] = 0;
         }
     });
 }
 
-extern "C" int chol_timing_read(const chol_sym* C, double* ms, int64_t* launches, double* flops) {
+extern "C" int chol_timing_read(const chol_sym* C, double* ms, int64_t* launches, double* flops, double* bytes) {
     return guarded([&] {
         OPF_CHECK(C, OPF_E_INVALID, "chol_timing_read: null handle");
         for (int q = 0; q < 5; q++) {
             if (ms) ms[q] = C->t_ms[q];
             if (launches) launches[q] = C->t_launch[q];
             if (flops) flops[q] = C->t_flops[q];
+            if (bytes) bytes[q] = C->t_bytes[q];
         }
     });
 }

@@ -102,7 +102,7 @@ def lib():
         L.chol_solve.argtypes = [VP, VP, VP, ctypes.c_int32, VP]
         L.chol_export_factor.argtypes = [VP, I64P, I32P, F64P]
         L.chol_timing.argtypes = [VP, ctypes.c_int]
-        L.chol_timing_read.argtypes = [VP, F64P, I64P, F64P]
+        L.chol_timing_read.argtypes = [VP, F64P, I64P, F64P, F64P]
         L.ipm_default_options.argtypes = [ctypes.POINTER(IpmOptions)]
         L.ipm_default_options.restype = None
         L.ipm_create.argtypes = [VP, ctypes.POINTER(IpmOptions), ctypes.POINTER(CholOptions), VP, ctypes.POINTER(VP)]
@@ -317,8 +317,11 @@ class Cholesky:
         ms = np.zeros(5)
         nl = np.zeros(5, np.int64)
         fl = np.zeros(5)
-        _check(lib().chol_timing_read(self._h, _p(ms, F64P), _p(nl, I64P), _p(fl, F64P)), "chol_timing_read")
-        return {k: {"ms": ms[i], "launches": int(nl[i]), "flops": fl[i]} for i, k in enumerate(self.TIMING_CATEGORIES)}
+        by = np.zeros(5)
+        _check(lib().chol_timing_read(self._h, _p(ms, F64P), _p(nl, I64P), _p(fl, F64P), _p(by, F64P)),
+               "chol_timing_read")
+        return {k: {"ms": ms[i], "launches": int(nl[i]), "flops": fl[i], "bytes": by[i]}
+                for i, k in enumerate(self.TIMING_CATEGORIES)}
 
     def export_factor(self, values=True):
         lp = np.zeros(self.n + 1, np.int64)
