@@ -39,7 +39,7 @@ def blocked_kernels_hash():
     the hardware-counter traffic recorded for the trailing update holds only while this is unchanged."""
     import hashlib
     src = open(os.path.join(HERE, "paper_2307_16830_amd", "csrc", "chol.hip")).read()
-    a = src.index("__device__ __forceinline__ int wave_potrf(")
+    a = src.index("constexpr int PW = ")
     b = src.index("\n}\n", src.index("void blk_syrk(")) + 3
     return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 

@@ -239,70 +239,137 @@ __device__ __forceinline__ double lane_value(double v, int l) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Cholesky of the kb x kb diagonal block at (k0, k0) by one wave: lane i keeps row i in registers and
-// the entries of column k of L are read lane by lane into scalar registers, so the update of a step
-// is a run of independent FMAs with no LDS round trip.  Rows >= kb are zero on entry and stay zero,
-// which makes the inner loop safe to run over the full tile width; entries above the diagonal are
-// updated too (never stored).  Returns the local index of the first rejected pivot or -1.
-__device__ __forceinline__ int wave_potrf(double (&a)[TB], int kb, int lane, double thr, double& rinv) {
-    int bad = -1;
-#pragma unroll
-    for (int k = 0; k < TB; k++) {
-        if (k < kb) {
-            double d = lane_value(a[k], k);
-            if (!(d > lane_value(thr, k))) {
-                if (bad < 0) bad = k;
-                d = 1.0;
-            }
-            const double r = sqrt(d);
-            const double lik = lane == k ? r : a[k] / r;
-            if (lane == k) rinv = 1.0 / r;
-            a[k] = lik;
-#pragma unroll
-            for (int j = k + 1; j < TB; j++) a[j] -= lik * lane_value(lik, j);
-        }
-    }
-    return bad;
+// Cholesky of the kb x kb diagonal block at (k0, k0) of front s by the NW = 4 waves of a work-group,
+// pipelined over the waves.  Lane i holds row i; wave w owns the 16 columns [16w, 16w + 16) in
+// registers.  A wave first applies every earlier column of L (produced by the waves before it) to its
+// own columns as soon as that column appears in LDS, then factors its own 16 pivots: pivot k is read
+// from lane k, scaled by a Newton-refined reciprocal square root, the finished column is published to
+// LDS, and the wave's later columns are updated with the column's entries read lane by lane.  A column
+// "appears" when its LDS slots no longer hold a sentinel NaN bit pattern that no computed value takes,
+// so there is no separate flag or fence.  A partial block is padded with the identity.  Besides writing
+// L_D into the front, the block is left in ldiag slot `slot` (64 x 64 column-major, identity padding)
+// with the reciprocal pivots in rdiag (ones past kb) for the panel solve, and status[s] is lowered to the
+// first rejected pivot (pivot <= tol |K_jj|, replaced by 1).  All NT threads must call it; `colbuf` is
+// 64 x 64 doubles of LDS (16-byte aligned) and `badmin` an int of LDS.
+constexpr int PW = 16;  // columns per wave in the pipelined diagonal-block Cholesky
+
+__device__ __forceinline__ double rsqrt_refined(double d) {
+    double y = __builtin_amdgcn_rsq(d);  // hardware estimate, then two Newton steps for 1/sqrt(d)
+    const double h = 0.5 * d;
+    y = y * fma(-h * y, y, 1.5);
+    y = y * fma(-h * y, y, 1.5);
+    return y;
 }
 
-// Cholesky of the diagonal block at (k0, k0) of front s by one wave (lane = row).  Besides writing L_D
-// into the front, it leaves a compact copy for the panel solve in slot `slot` of ldiag (64 x 64,
-// column-major, a partial block padded with the identity) and the reciprocals of its pivots in rdiag
-// (padded with ones), and lowers status[s] to the first rejected pivot.
-__device__ __forceinline__ void potrf_block(int s, int k0, int slot, int lane, const int32_t* __restrict__ first,
+constexpr unsigned long long SENTINEL_BITS = 0x7ff4dead00000000ULL;
+
+__device__ __forceinline__ bool is_sentinel(double v) {
+    return (unsigned long long)__double_as_longlong(v) == SENTINEL_BITS;
+}
+
+__device__ __forceinline__ void potrf_block(int s, int k0, int slot, const int32_t* __restrict__ first,
                                             const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
                                             const int64_t* __restrict__ foff, double* __restrict__ fronts,
                                             double* __restrict__ ldiag, double* __restrict__ rdiag,
-                                            int32_t* __restrict__ status, const PivotRef& pr) {
+                                            int32_t* __restrict__ status, const PivotRef& pr, double* colbuf,
+                                            int* badmin) {
+    const int lane = threadIdx.x % 64;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
     const int m = mrows[s];
     const int kb = min(TB, ncol[s] - k0);
     double* F = fronts + foff[s] + (int64_t)k0 + (int64_t)m * k0;
     const int p0 = first[s] + k0;
-    const double thr = lane < kb ? pr.thresh(p0 + lane) : 0.0;
-    double a[TB];
+    const double sentinel = __longlong_as_double((long long)SENTINEL_BITS);
+    for (int e = threadIdx.x; e < TB * TB; e += NT) colbuf[e] = sentinel;
+    if (threadIdx.x == 0) *badmin = INT_MAX;
+    const double thr = lane < kb ? pr.thresh(p0 + lane) : 0.0;  // lane k holds pivot k's threshold
+    double a[PW];
 #pragma unroll
-    for (int j = 0; j < TB; j++) a[j] = (j < kb && lane < kb && j <= lane) ? F[lane + (int64_t)m * j] : 0.0;
-    double rinv = 1.0;
-    const int bad = wave_potrf(a, kb, lane, thr, rinv);
+    for (int c = 0; c < PW; c++) {
+        const int j = PW * w + c;
+        a[c] = (j < kb && lane < kb) ? (j <= lane ? F[lane + (int64_t)m * j] : 0.0) : (j == lane ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    // columns of the waves before this one, two at a time
+    for (int k = 0; k < PW * w; k += 2) {
+        double l0, l1;
+        double2 u0[PW / 2], u1[PW / 2];
+        int spins = 0;
+        bool wait;
+        do {
+            asm volatile("" ::: "memory");
+            l0 = colbuf[TB * k + lane];
+            l1 = colbuf[TB * (k + 1) + lane];
 #pragma unroll
-    for (int j = 0; j < TB; j++)
-        if (j < kb && lane < kb && j <= lane) F[lane + (int64_t)m * j] = a[j];
+            for (int q = 0; q < PW / 2; q++) {
+                u0[q] = *reinterpret_cast<const double2*>(&colbuf[TB * k + PW * w + 2 * q]);
+                u1[q] = *reinterpret_cast<const double2*>(&colbuf[TB * (k + 1) + PW * w + 2 * q]);
+            }
+            bool pending = is_sentinel(l0) || is_sentinel(l1);
+#pragma unroll
+            for (int q = 0; q < PW / 2; q++)
+                pending = pending || is_sentinel(u0[q].x) || is_sentinel(u0[q].y) || is_sentinel(u1[q].x) ||
+                          is_sentinel(u1[q].y);
+            // bounded: the producing waves belong to this work-group and always progress
+            wait = __any(pending) && ++spins < (1 << 22);
+        } while (wait);
+#pragma unroll
+        for (int q = 0; q < PW / 2; q++) {
+            a[2 * q] = fma(-l0, u0[q].x, a[2 * q]);
+            a[2 * q + 1] = fma(-l0, u0[q].y, a[2 * q + 1]);
+        }
+#pragma unroll
+        for (int q = 0; q < PW / 2; q++) {
+            a[2 * q] = fma(-l1, u1[q].x, a[2 * q]);
+            a[2 * q + 1] = fma(-l1, u1[q].y, a[2 * q + 1]);
+        }
+    }
+    // own pivots
+    int bad = INT_MAX;
+    double myrinv = 1.0;
+#pragma unroll
+    for (int c = 0; c < PW; c++) {
+        const int k = PW * w + c;
+        double d = lane_value(a[c], k);
+        if (!(d > lane_value(thr, k))) {
+            bad = min(bad, k);
+            d = 1.0;
+        }
+        const double rinv = rsqrt_refined(d);
+        const double lik = lane == k ? d * rinv : a[c] * rinv;
+        if (lane == k) myrinv = rinv;
+        a[c] = lik;
+        colbuf[TB * k + lane] = lik;
+        asm volatile("" ::: "memory");  // publish now, not after the wave's later pivots
+#pragma unroll
+        for (int c2 = c + 1; c2 < PW; c2++) a[c2] = fma(-lik, lane_value(lik, PW * w + c2), a[c2]);
+    }
+    if (lane == 0 && bad < kb) atomicMin(badmin, bad);
+    // results: the front (valid lower part), the compact copy and the reciprocal pivots
     double* Lc = ldiag + (int64_t)slot * TB * TB + lane;
 #pragma unroll
-    for (int j = 0; j < TB; j++) Lc[TB * j] = (j < kb && lane < kb) ? (j <= lane ? a[j] : 0.0) : (j == lane ? 1.0 : 0.0);
-    rdiag[(int64_t)slot * TB + lane] = lane < kb ? rinv : 1.0;
-    if (lane == 0 && bad >= 0) status[s] = min(status[s], p0 + bad);
+    for (int c = 0; c < PW; c++) {
+        const int j = PW * w + c;
+        if (j < kb && lane < kb && j <= lane) F[lane + (int64_t)m * j] = a[c];
+        Lc[TB * j] = j <= lane ? a[c] : 0.0;
+    }
+    // lane i of the wave owning column i holds that pivot's reciprocal
+    if (lane >= PW * w && lane < PW * w + PW) rdiag[(int64_t)slot * TB + lane] = myrinv;
+    __syncthreads();
+    if (threadIdx.x == 0 && *badmin < INT_MAX) status[s] = min(status[s], p0 + *badmin);
 }
 
 // Diagonal blocks of the first blocked step of each front (later steps factor theirs inside the
 // trailing update of the step before, see blk_syrk).
-__global__ __launch_bounds__(64) void blk_potrf(const int32_t* __restrict__ it, const int32_t* __restrict__ first,
+__global__ __launch_bounds__(NT) void blk_potrf(const int32_t* __restrict__ it, const int32_t* __restrict__ first,
                                                 const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
                                                 const int64_t* __restrict__ foff, double* __restrict__ fronts,
                                                 double* __restrict__ ldiag, double* __restrict__ rdiag,
                                                 int32_t* __restrict__ status, PivotRef pr) {
-    potrf_block(it[2 * blockIdx.x], it[2 * blockIdx.x + 1], blockIdx.x, threadIdx.x, first, ncol, mrows, foff,
-                fronts, ldiag, rdiag, status, pr);
+    __shared__ __attribute__((aligned(16))) double colbuf[TB * TB];
+    __shared__ int badmin;
+    potrf_block(it[2 * blockIdx.x], it[2 * blockIdx.x + 1], blockIdx.x, first, ncol, mrows, foff, fronts, ldiag,
+                rdiag, status, pr, colbuf, &badmin);
 }
 
 // X <- X L_D^{-T} below the diagonal block: one thread per panel row, 64 rows per work-group, the row in
@@ -380,8 +447,12 @@ __global__ __launch_bounds__(NT) void blk_syrk(const int32_t* __restrict__ it, i
                                                const int32_t* __restrict__ first, double* __restrict__ ldiag,
                                                double* __restrict__ rdiag, int32_t* __restrict__ status,
                                                PivotRef pr) {
-    __shared__ double Pi[KC][ST + 1];
-    __shared__ double Pj[KC][ST + 1];
+    // LDS: the two panel chunks, reused by the fused diagonal-block Cholesky as its 64 x 64 column buffer
+    __shared__ __attribute__((aligned(16))) double lds[2 * KC * (ST + 1)];
+    __shared__ int badmin;
+    double(*Pi)[ST + 1] = reinterpret_cast<double(*)[ST + 1]>(lds);
+    double(*Pj)[ST + 1] = reinterpret_cast<double(*)[ST + 1]>(lds + KC * (ST + 1));
+    static_assert(2 * KC * (ST + 1) >= TB * TB, "column buffer fits in the panel buffers");
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int qr = (wave / 2) * 64, qc = (wave % 2) * 64;
     const int li = lane % 16, lk = lane / 16;
@@ -453,9 +524,9 @@ __global__ __launch_bounds__(NT) void blk_syrk(const int32_t* __restrict__ it, i
                     }
         }
         if (pslot && pslot[item] >= 0) {
-            __syncthreads();  // the tile's stores are visible to the whole work-group
-            if (wave == 0)
-                potrf_block(s, rj0, pslot[item], lane, first, ncol, mrows, foff, fronts, ldiag, rdiag, status, pr);
+            __syncthreads();  // the tile's stores are visible to the whole work-group; LDS is free
+            potrf_block(s, rj0, pslot[item], first, ncol, mrows, foff, fronts, ldiag, rdiag, status, pr, lds,
+                        &badmin);
         }
     }
 }
@@ -1218,7 +1289,7 @@ void chol_factor_enqueue(chol_sym* C, const double* kval, hipStream_t st, double
             hipEvent_t ev_panel = C->ev_la[2 * (q - q0)], ev_rest = C->ev_la[2 * (q - q0) + 1];
             if (q == q0 && S.p1 > S.p0) {  // later steps factor their diagonal blocks in the update before
                 tmark(C, st, 2);
-                hipLaunchKernelGGL(blk_potrf, dim3(S.p1 - S.p0), dim3(64), 0, st, C->potrf_it.p + 2 * S.p0,
+                hipLaunchKernelGGL(blk_potrf, dim3(S.p1 - S.p0), dim3(NT), 0, st, C->potrf_it.p + 2 * S.p0,
                                    C->first.p, C->ncol.p, C->mrows.p, C->foff.p, C->fronts.p, C->ldiag.p,
                                    C->rdiag.p, C->status.p, pr);
                 OPF_LAUNCH_CHECK();
