@@ -79,10 +79,10 @@ struct chol_sym {
     DBuf<int32_t> status;
     DBuf<double> fronts, upd, work, ybuf;
     DBuf<double> ldiag, rdiag;  // compact diagonal blocks and reciprocal pivots of one blocked step
-    // sync-free solves of wide fronts: one ready flag per 64-block, compared with a per-sweep epoch
-    std::vector<int64_t> h_flag_off;  // per supernode (wide fronts only)
-    DBuf<int32_t> sflags, sfault;
-    int32_t epoch = 0;
+    // sync-free solves of wide fronts
+    std::vector<int64_t> h_flag_off;  // per supernode (wide fronts only): offset of its blocks in zx
+    DBuf<double> zx;                  // solved 64-blocks of the wide fronts' sweeps
+    DBuf<int32_t> sfault;
     Deferred dev;  // pending uploads, run at the first device use
     // optional per-category kernel timing (assemble, small, potrf, trsm, syrk): bit mask of categories
     int timing = 0;
@@ -634,20 +634,15 @@ __global__ __launch_bounds__(NT) void solve_bwd(const int32_t* __restrict__ list
 // ---------------------------------------------------------------- sync-free solves for wide fronts
 // A front with many pivots is solved by one launch per sweep whose work-groups each own a 64-row
 // (forward) or 64-column (backward) block of the front.  A block's work-group multiplies its part of
-// L with every solved block as soon as that block's ready flag carries the sweep's epoch, then
-// solves with its own diagonal block in registers (one wave, pivots read lane by lane) and publishes
-// its block and flag.  Every wait is on a lower-numbered work-group, and work-groups are dispatched
-// in index order, so a waiting work-group never holds back the one it waits for.  Solved blocks and
-// flags go through device-coherent (agent-scope) stores and loads, because the work-groups of a
-// launch sit on different dies with separate L2 caches.  A wait is bounded: past the spin limit the
-// fault word is raised and the work-group goes on (the result is then invalid and reported).
+// L with every solved block as soon as that block has arrived, then solves with its own diagonal block
+// in registers (one wave, pivots read lane by lane) and publishes its block.  Every wait is on a
+// lower-numbered work-group, and work-groups are dispatched in index order, so a waiting work-group
+// never holds back the one it waits for.  Solved blocks go through device-coherent (agent-scope) stores
+// and loads, because the work-groups of a launch sit on dies with separate L2 caches.  A wait is
+// bounded: past the spin limit the fault word is raised and the work-group goes on (the result is then
+// invalid and reported).
 constexpr int WIDE = 256;  // fronts with at least this many pivots use the sync-free solves
 constexpr int SB = 64;     // block edge of the sync-free solves
-
-__global__ void fill_i32(int64_t n, int32_t* __restrict__ p, int32_t v) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n) p[k] = v;
-}
 
 __device__ __forceinline__ void store_coherent(double* p, double v) {
     __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), (unsigned long long)__double_as_longlong(v),
@@ -657,24 +652,6 @@ __device__ __forceinline__ void store_coherent(double* p, double v) {
 __device__ __forceinline__ double load_coherent(const double* p) {
     return __longlong_as_double((long long)__hip_atomic_load(
         reinterpret_cast<unsigned long long*>(const_cast<double*>(p)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-}
-
-// Spin until *flag == epoch.  Once one wait of a work-group has timed out (alive = false) its later
-// waits return at once, so a work-group spends at most one spin limit (about a second) waiting.
-__device__ __forceinline__ void wait_flag(int32_t* flag, int32_t epoch, int32_t* fault, bool& alive) {
-    if (!alive) return;
-    for (int it = 0; it < (1 << 20); it++) {
-        if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch) return;
-        __builtin_amdgcn_s_sleep(2);
-    }
-    alive = false;
-    __hip_atomic_store(fault, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Publish a solved block: all its stores complete before the flag is raised.
-__device__ __forceinline__ void publish(int32_t* flag, int32_t epoch, bool leader) {
-    __builtin_amdgcn_s_waitcnt(0);
-    if (leader) __hip_atomic_store(flag, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // forward, step 0: w = [y(own rows), 0] + children's partial results (one work-group per front)
@@ -701,17 +678,46 @@ __global__ __launch_bounds__(NT) void sfwd_gather(const int32_t* __restrict__ li
     }
 }
 
+// Solved blocks travel through an exchange buffer zx (64 doubles per pivot block) that is filled with the
+// sentinel NaN pattern before each sweep: a block is ready when none of its 64 entries is the sentinel,
+// so the data is its own ready flag (one memory round trip per hand-over instead of two).
+__global__ void fill_sentinel(int64_t n, double* __restrict__ p) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) p[k] = __longlong_as_double((long long)SENTINEL_BITS);
+}
+
+// Wave 0 waits until block c of zx is complete and leaves it in zs (entries past kc as 0); bounded: after
+// the spin limit the fault word is raised and the block is taken as it is.
+__device__ __forceinline__ void take_block(const double* __restrict__ zx, int c, int kc, double* zs,
+                                           int32_t* __restrict__ fault, bool& alive) {
+    if (threadIdx.x < 64) {
+        double v;
+        int spins = 0;
+        while (true) {
+            v = load_coherent(zx + SB * c + threadIdx.x);
+            if (!alive || !__any(is_sentinel(v))) break;
+            if (++spins > (1 << 20)) {
+                alive = false;
+                if (threadIdx.x == 0) __hip_atomic_store(fault, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        zs[threadIdx.x] = (int)threadIdx.x < kc ? v : 0.0;
+    }
+}
+
 // forward sweep of one wide front.  Work-group g < nblk owns pivot rows [64g, 64g + 64): it subtracts
-// L(rows, block c) z_c for every c < g, solves with L(g, g) and publishes z_g in y.  The remaining
-// work-groups own 64-row blocks of the rows below the pivots and write their partial result to upd.
-// Thread (i, q) = (row in block, quarter of the 64 columns of a block).
-__global__ __launch_bounds__(NT) void wide_fwd(int s, int32_t epoch, int32_t* __restrict__ flags,
-                                               int32_t* __restrict__ fault, const int32_t* __restrict__ first,
-                                               const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
-                                               const int64_t* __restrict__ foff, const int64_t* __restrict__ roff,
-                                               const int64_t* __restrict__ uoff, const double* __restrict__ fronts,
-                                               const double* __restrict__ work, double* __restrict__ upd,
-                                               double* __restrict__ y) {
+// L(rows, block c) z_c for every c < g as soon as z_c is in zx, solves with L(g, g) and publishes z_g
+// (to zx, device-coherent, and to y).  The remaining work-groups own 64-row blocks of the rows below
+// the pivots and write their partial result to upd.  Thread (i, q) = (row in block, quarter of the 64
+// columns of a block).
+__global__ __launch_bounds__(NT) void wide_fwd(int s, double* __restrict__ zx, int32_t* __restrict__ fault,
+                                               const int32_t* __restrict__ first, const int32_t* __restrict__ ncol,
+                                               const int32_t* __restrict__ mrows, const int64_t* __restrict__ foff,
+                                               const int64_t* __restrict__ roff, const int64_t* __restrict__ uoff,
+                                               const double* __restrict__ fronts, const double* __restrict__ work,
+                                               double* __restrict__ upd, double* __restrict__ y) {
     __shared__ double zs[SB];
     __shared__ double red[NT / 64][SB];
     const int m = mrows[s], nn = ncol[s], f = first[s];
@@ -741,12 +747,11 @@ __global__ __launch_bounds__(NT) void wide_fwd(int s, int32_t epoch, int32_t* __
             const int j = 16 * q + jj;
             lv[jj] = (rowok && j < kc) ? Lr[(int64_t)m * (c0 + j)] : 0.0;
         }
-        if (threadIdx.x == 0) wait_flag(flags + c, epoch, fault, alive);
-        __syncthreads();
-        if (threadIdx.x < SB) zs[threadIdx.x] = (int)threadIdx.x < kc ? load_coherent(y + f + c0 + threadIdx.x) : 0.0;
+        take_block(zx, c, kc, zs, fault, alive);
         __syncthreads();
 #pragma unroll
         for (int jj = 0; jj < 16; jj++) acc += lv[jj] * zs[16 * q + jj];
+        __syncthreads();
     }
     red[q][i] = acc;
     __syncthreads();
@@ -763,20 +768,19 @@ __global__ __launch_bounds__(NT) void wide_fwd(int s, int32_t epoch, int32_t* __
             wi = i == j ? zj : (i > j ? wi - a[j] * zj : wi);
         }
     }
-    if (rowok) store_coherent(y + f + r0 + i, wi);
-    publish(flags + g, epoch, i == 0);
+    store_coherent(zx + SB * g + i, rowok ? wi : 0.0);
+    if (rowok) y[f + r0 + i] = wi;
 }
 
 // backward sweep of one wide front.  Work-group g owns pivot block b = nblk - 1 - g (columns
 // [64b, 64b + 64)): it subtracts L(rows, b)^T x for the rows below the pivots (solved by the
-// ancestors) and for every later block c > b as soon as it is published, then solves with L(b, b)^T
-// and publishes x_b in y.  Thread (j, q) = (column in block, quarter of the 64 rows of a block).
-__global__ __launch_bounds__(NT) void wide_bwd(int s, int32_t epoch, int32_t* __restrict__ flags,
-                                               int32_t* __restrict__ fault, const int32_t* __restrict__ first,
-                                               const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
-                                               const int64_t* __restrict__ foff, const int64_t* __restrict__ roff,
-                                               const int32_t* __restrict__ rows, const double* __restrict__ fronts,
-                                               double* __restrict__ y) {
+// ancestors) and for every later block c > b as soon as x_c is in zx, then solves with L(b, b)^T
+// and publishes x_b (to zx and y).  Thread (j, q) = (column in block, quarter of the 64 rows of a block).
+__global__ __launch_bounds__(NT) void wide_bwd(int s, double* __restrict__ zx, int32_t* __restrict__ fault,
+                                               const int32_t* __restrict__ first, const int32_t* __restrict__ ncol,
+                                               const int32_t* __restrict__ mrows, const int64_t* __restrict__ foff,
+                                               const int64_t* __restrict__ roff, const int32_t* __restrict__ rows,
+                                               const double* __restrict__ fronts, double* __restrict__ y) {
     __shared__ double xs[SB];
     __shared__ double red[NT / 64][SB];
     const int m = mrows[s], nn = ncol[s], f = first[s];
@@ -818,9 +822,8 @@ __global__ __launch_bounds__(NT) void wide_bwd(int s, int32_t epoch, int32_t* __
             const int r = 16 * q + ii;
             lv[ii] = (colok && r < nr) ? Lc[cr0 + r] : 0.0;
         }
-        if (threadIdx.x == 0) wait_flag(flags + (nblk - 1 - c), epoch, fault, alive);
         __syncthreads();
-        if (threadIdx.x < SB) xs[threadIdx.x] = (int)threadIdx.x < nr ? load_coherent(y + f + cr0 + threadIdx.x) : 0.0;
+        take_block(zx, c, nr, xs, fault, alive);
         __syncthreads();
 #pragma unroll
         for (int ii = 0; ii < 16; ii++) acc += lv[ii] * xs[16 * q + ii];
@@ -836,8 +839,8 @@ __global__ __launch_bounds__(NT) void wide_bwd(int s, int32_t epoch, int32_t* __
             tj = j == t ? xt : (j < t ? tj - a[t] * xt : tj);
         }
     }
-    if (colok) store_coherent(y + f + c0 + j, tj);
-    publish(flags + g, epoch, j == 0);
+    store_coherent(zx + SB * b + j, colok ? tj : 0.0);
+    if (colok) y[f + c0 + j] = tj;
 }
 
 }  // namespace
@@ -1132,7 +1135,7 @@ static void build_numeric_plan(chol_sym* C, const std::vector<int32_t>& colptr, 
             C->h_flag_off[s] = nflags;
             nflags += (C->h_ncol[s] + SB - 1) / SB;
         }
-    C->dev.upload(C->sflags, std::vector<int32_t>(std::max<int64_t>(nflags, 1), 0));
+    C->dev.alloc(C->zx, std::max<int64_t>(nflags, 1) * SB);
     C->dev.upload(C->sfault, std::vector<int32_t>(1, 0));
 }
 
@@ -1366,13 +1369,6 @@ void chol_solve_enqueue(chol_sym* C, const double* b, double* x, hipStream_t st)
     C->dev.run();
     const int n = C->n;
     double* y = C->ybuf.p;
-    if (C->epoch > INT32_MAX - 4) {  // epochs restart from 0 once every flag is cleared
-        const int64_t nf = C->sflags.n;
-        hipLaunchKernelGGL(fill_i32, dim3(ceil_div(nf, 256)), dim3(256), 0, st, nf, C->sflags.p, 0);
-        OPF_LAUNCH_CHECK();
-        C->epoch = 0;
-    }
-    const int32_t ef = ++C->epoch, eb = ++C->epoch;
     hipLaunchKernelGGL(permute_in, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, C->perm.p, b, y);
     OPF_LAUNCH_CHECK();
     for (int l = 0; l < C->nlevels; l++) {
@@ -1393,9 +1389,12 @@ void chol_solve_enqueue(chol_sym* C, const double* b, double* x, hipStream_t st)
                 const int s = C->lvl_wide[q];
                 const int m = C->h_mrows[s], nn = C->h_ncol[s];
                 const int g = (nn + SB - 1) / SB + (m - nn + SB - 1) / SB;
-                hipLaunchKernelGGL(wide_fwd, dim3(g), dim3(NT), 0, st, s, ef, C->sflags.p + C->h_flag_off[s],
-                                   C->sfault.p, C->first.p, C->ncol.p, C->mrows.p, C->foff.p, C->roff.p, C->uoff.p,
-                                   C->fronts.p, C->work.p, C->upd.p, y);
+                double* zx = C->zx.p + C->h_flag_off[s] * SB;
+                const int64_t nz = (int64_t)((nn + SB - 1) / SB) * SB;
+                hipLaunchKernelGGL(fill_sentinel, dim3(ceil_div(nz, 256)), dim3(256), 0, st, nz, zx);
+                OPF_LAUNCH_CHECK();
+                hipLaunchKernelGGL(wide_fwd, dim3(g), dim3(NT), 0, st, s, zx, C->sfault.p, C->first.p, C->ncol.p,
+                                   C->mrows.p, C->foff.p, C->roff.p, C->uoff.p, C->fronts.p, C->work.p, C->upd.p, y);
                 OPF_LAUNCH_CHECK();
             }
         }
@@ -1405,9 +1404,12 @@ void chol_solve_enqueue(chol_sym* C, const double* b, double* x, hipStream_t st)
         for (int q = w0; q < w1; q++) {
             const int s = C->lvl_wide[q];
             const int nn = C->h_ncol[s];
-            hipLaunchKernelGGL(wide_bwd, dim3((nn + SB - 1) / SB), dim3(NT), 0, st, s, eb,
-                               C->sflags.p + C->h_flag_off[s], C->sfault.p, C->first.p, C->ncol.p, C->mrows.p,
-                               C->foff.p, C->roff.p, C->rows.p, C->fronts.p, y);
+            double* zx = C->zx.p + C->h_flag_off[s] * SB;
+            const int64_t nz = (int64_t)((nn + SB - 1) / SB) * SB;
+            hipLaunchKernelGGL(fill_sentinel, dim3(ceil_div(nz, 256)), dim3(256), 0, st, nz, zx);
+            OPF_LAUNCH_CHECK();
+            hipLaunchKernelGGL(wide_bwd, dim3((nn + SB - 1) / SB), dim3(NT), 0, st, s, zx, C->sfault.p, C->first.p,
+                               C->ncol.p, C->mrows.p, C->foff.p, C->roff.p, C->rows.p, C->fronts.p, y);
             OPF_LAUNCH_CHECK();
         }
         int q0 = C->lvl_narrow_ptr[l], q1 = C->lvl_narrow_ptr[l + 1];
