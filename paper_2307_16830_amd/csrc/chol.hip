@@ -73,9 +73,7 @@ struct chol_sym {
     DBuf<int32_t> lvl_sn_d, lvl_small_d, lvl_narrow_d, lvl_wide_d;
     DBuf<int32_t> potrf_it, trsm_it, syrk_it;  // packed items
     DBuf<int32_t> next_slot;  // per trailing-update item: slot of the next panel's diagonal block, or -1
-    // look-ahead: the trailing update past the next panel runs on a second stream
-    hipStream_t st2 = nullptr;
-    std::vector<hipEvent_t> ev_la;
+
     DBuf<int32_t> status;
     DBuf<double> fronts, upd, work, ybuf;
     DBuf<double> ldiag, rdiag;  // compact diagonal blocks and reciprocal pivots of one blocked step
@@ -97,8 +95,6 @@ struct chol_sym {
     std::vector<double> step_syrk_bytes;  // and its algorithmic HBM bytes (C read + written, panel read once)
     ~chol_sym() {
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
-        for (hipEvent_t e : ev_la) (void)hipEventDestroy(e);
-        if (st2) (void)hipStreamDestroy(st2);
     }
 };
 
@@ -430,20 +426,20 @@ __global__ __launch_bounds__(TR) void blk_trsm(const int32_t* __restrict__ it, c
 // the panel rows are staged through LDS in chunks of 16 columns.
 typedef double double4_t __attribute__((ext_vector_type(4)));
 constexpr int KC = 16;
-constexpr int REST_GRID = 224;  // work-groups of the off-critical-path update (of 256 compute units)
 
 // Item: (front, k0, first row ri0, first column rj0) of a tile of up to 128 rows and cw columns.  The
-// grid may be smaller than the item count (work-groups loop over items), which leaves compute units
-// free for the launches of the critical path running beside it.  The accumulators start from the
-// tile of C and the row panel is negated on its way into LDS, so the MFMAs accumulate C - Pi Pj^T and
-// the tile is read once, at the start, where its latency overlaps the first panel loads.
-// With pslot given (the update of the next panel's 64 columns), the work-group holding a front's
-// diagonal tile goes on to factor the next panel's diagonal block, which it has just brought up to
-// date, into ldiag slot pslot[item] (-1: no such block); that saves the diagonal-block launch.
-__global__ __launch_bounds__(NT) void blk_syrk(const int32_t* __restrict__ it, int nitems,
+// accumulators start from the tile of C and the row panel is negated on its way into LDS, so the MFMAs
+// accumulate C - Pi Pj^T and the tile is read once, at the start, where its latency overlaps the first
+// panel loads.
+// One launch per blocked step covers the whole trailing update: the first nnext items are 128 x 64 tiles of
+// the next panel's 64 columns, the rest 128 x 128 tiles of the columns after it.  The work-group holding
+// a front's next-panel diagonal tile goes on to factor that panel's diagonal block, which it has just
+// brought up to date, into ldiag slot pslot[item] (-1: no such block), while the other work-groups are
+// still updating the rest: the diagonal-block Cholesky of step k+1 hides under the update of step k.
+__global__ __launch_bounds__(NT) void blk_syrk(const int32_t* __restrict__ it, int nitems, int nnext,
                                                const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
                                                const int64_t* __restrict__ foff, double* __restrict__ fronts,
-                                               int cw, const int32_t* __restrict__ pslot,
+                                               const int32_t* __restrict__ pslot,
                                                const int32_t* __restrict__ first, double* __restrict__ ldiag,
                                                double* __restrict__ rdiag, int32_t* __restrict__ status,
                                                PivotRef pr) {
@@ -459,6 +455,7 @@ __global__ __launch_bounds__(NT) void blk_syrk(const int32_t* __restrict__ it, i
     for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
         const int s = it[4 * item], k0 = it[4 * item + 1];
         const int ri0 = it[4 * item + 2], rj0 = it[4 * item + 3];
+        const int cw = item < nnext ? TB : ST;
         const int m = mrows[s];
         const int kb = min(TB, ncol[s] - k0);
         const int nri = min(ST, m - ri0), nrj = min(cw, m - rj0);
@@ -1079,8 +1076,8 @@ static void build_numeric_plan(chol_sym* C, const std::vector<int32_t>& colptr, 
                 if (m <= TB || k * TB >= nn) continue;
                 double kb = std::min(TB, nn - k * TB), r = m - k * TB - kb;
                 fl += r * (r + 1) * kb;  // symmetric rank-kb update of an r x r lower triangle
-                // both launches of the step: every lower entry of the r x r block read and written once
-                // (16 B); the panel rows read once per launch (the next-panel launch and the rest)
+                // every lower entry of the r x r block read and written once (16 B); the panel rows read
+                // once by the next-panel tiles and once by the tiles after them
                 const double rest = std::max(0.0, r - TB);
                 by += 16.0 * r * (r + 1) / 2 + 8.0 * kb * (r + rest);
             }
@@ -1259,14 +1256,6 @@ static void tcollect(chol_sym* C) {
 
 void chol_factor_enqueue(chol_sym* C, const double* kval, hipStream_t st, double pivot_tol) {
     C->dev.run();
-    if (!C->st2) {
-        OPF_HIP(hipStreamCreateWithFlags(&C->st2, hipStreamNonBlocking));
-        size_t need = 0;
-        for (int l = 0; l < C->nlevels; l++)
-            need = std::max<size_t>(need, 2 * (size_t)(C->lvl_step_ptr[l + 1] - C->lvl_step_ptr[l]));
-        C->ev_la.resize(need, nullptr);
-        for (auto& e : C->ev_la) OPF_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    }
     const PivotRef pr{kval, C->kdiagpos.p, pivot_tol};
     for (int l = 0; l < C->nlevels; l++) {
         int t0 = C->asm_ptr[l], t1 = C->asm_ptr[l + 1];
@@ -1289,7 +1278,6 @@ void chol_factor_enqueue(chol_sym* C, const double* kval, hipStream_t st, double
         const int q0 = C->lvl_step_ptr[l], q1 = C->lvl_step_ptr[l + 1];
         for (int q = q0; q < q1; q++) {
             const chol_sym::Step& S = C->steps[q];
-            hipEvent_t ev_panel = C->ev_la[2 * (q - q0)], ev_rest = C->ev_la[2 * (q - q0) + 1];
             if (q == q0 && S.p1 > S.p0) {  // later steps factor their diagonal blocks in the update before
                 tmark(C, st, 2);
                 hipLaunchKernelGGL(blk_potrf, dim3(S.p1 - S.p0), dim3(NT), 0, st, C->potrf_it.p + 2 * S.p0,
@@ -1305,34 +1293,19 @@ void chol_factor_enqueue(chol_sym* C, const double* kval, hipStream_t st, double
                 OPF_LAUNCH_CHECK();
                 tmark(C, st, 3);
             }
-            OPF_HIP(hipEventRecord(ev_panel, st));
-            // the previous step's update of the later columns also covers this step's next panel
-            if (q > q0) OPF_HIP(hipStreamWaitEvent(st, C->ev_la[2 * (q - q0) - 1], 0));
-            if (S.s1 > S.s0) {
+            if (S.r1 > S.s0) {
                 tmark(C, st, 4);
-                hipLaunchKernelGGL(blk_syrk, dim3(S.s1 - S.s0), dim3(NT), 0, st, C->syrk_it.p + 4 * S.s0, S.s1 - S.s0,
-                                   C->ncol.p, C->mrows.p, C->foff.p, C->fronts.p, TB, C->next_slot.p + S.s0,
+                hipLaunchKernelGGL(blk_syrk, dim3(S.r1 - S.s0), dim3(NT), 0, st, C->syrk_it.p + 4 * S.s0, S.r1 - S.s0,
+                                   S.s1 - S.s0, C->ncol.p, C->mrows.p, C->foff.p, C->fronts.p, C->next_slot.p + S.s0,
                                    C->first.p, C->ldiag.p, C->rdiag.p, C->status.p, pr);
                 OPF_LAUNCH_CHECK();
                 tmark(C, st, 4);
             }
-            OPF_HIP(hipStreamWaitEvent(C->st2, ev_panel, 0));
-            if (S.r1 > S.r0) {
-                tmark(C, C->st2, 4);
-                hipLaunchKernelGGL(blk_syrk, dim3(std::min(S.r1 - S.r0, REST_GRID)), dim3(NT), 0, C->st2,
-                                   C->syrk_it.p + 4 * S.r0, S.r1 - S.r0, C->ncol.p, C->mrows.p, C->foff.p,
-                                   C->fronts.p, ST, nullptr, nullptr, nullptr, nullptr, nullptr, pr);
-                OPF_LAUNCH_CHECK();
-                tmark(C, C->st2, 4);
-            }
-            OPF_HIP(hipEventRecord(ev_rest, C->st2));
             if (C->timing & (1 << 4)) {
                 C->t_flops[4] += C->step_syrk_flops[q];
                 C->t_bytes[4] += C->step_syrk_bytes[q];
             }
         }
-        // the next level assembles from this level's update matrices
-        if (q1 > q0) OPF_HIP(hipStreamWaitEvent(st, C->ev_la[2 * (q1 - q0) - 1], 0));
     }
 }
 
