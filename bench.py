@@ -175,6 +175,11 @@ def main():
                                f"n={M.n}, m={M.m}, tol={args.tol}",
                    "global_batch": 1, "parallelism": "single GPU"},
         "stages_ms": stage,
+        # algorithmic HBM rates of the two memory-bound stages (values only; index maps and template
+        # parameters excluded): the Hessian evaluation reads x, y and writes H; the condensed assembly
+        # reads H, J, D, Sigma_x and writes K
+        "stage_gbs": {"ad_hessian": 8.0 * (M.n + M.m + M.nnzh) / (stage["t_ad"] * 1e-3) / 1e9,
+                      "assembly": 8.0 * (M.nnzh + M.nnzj + M.m + M.n + M.nnzk) / (stage["t_assembly"] * 1e-3) / 1e9},
         "analysis_s": t_analyze,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": recorded_traffic(),

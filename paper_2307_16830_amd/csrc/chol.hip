@@ -443,12 +443,12 @@ __global__ __launch_bounds__(NT) void blk_syrk(const int32_t* __restrict__ it, i
                                                const int32_t* __restrict__ first, double* __restrict__ ldiag,
                                                double* __restrict__ rdiag, int32_t* __restrict__ status,
                                                PivotRef pr) {
-    // LDS: the two panel chunks, reused by the fused diagonal-block Cholesky as its 64 x 64 column buffer
-    __shared__ __attribute__((aligned(16))) double lds[2 * KC * (ST + 1)];
+    // LDS: both 64-column panel slices of the tile at once (132 KB, so one load phase and one barrier per
+    // tile), reused by the fused diagonal-block Cholesky as its 64 x 64 column buffer
+    __shared__ __attribute__((aligned(16))) double lds[2 * TB * (ST + 1)];
     __shared__ int badmin;
     double(*Pi)[ST + 1] = reinterpret_cast<double(*)[ST + 1]>(lds);
-    double(*Pj)[ST + 1] = reinterpret_cast<double(*)[ST + 1]>(lds + KC * (ST + 1));
-    static_assert(2 * KC * (ST + 1) >= TB * TB, "column buffer fits in the panel buffers");
+    double(*Pj)[ST + 1] = reinterpret_cast<double(*)[ST + 1]>(lds + TB * (ST + 1));
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int qr = (wave / 2) * 64, qc = (wave % 2) * 64;
     const int li = lane % 16, lk = lane / 16;
@@ -477,23 +477,22 @@ __global__ __launch_bounds__(NT) void blk_syrk(const int32_t* __restrict__ it, i
                     const int gi = ri0 + i, gj = rj0 + j;
                     acc[a][b][r] = (active && i < nri && j < nrj && gi >= gj) ? F[(int64_t)gi + (int64_t)m * gj] : 0.0;
                 }
-        for (int t0 = 0; t0 < kb; t0 += KC) {
-            __syncthreads();
-            for (int e = threadIdx.x; e < ST * KC; e += NT) {
-                const int r = e % ST, t = e / ST;
-                const int tt = t0 + t;
-                double a = 0.0, b = 0.0;
-                if (tt < kb) {
-                    if (r < nri) a = F[(int64_t)(ri0 + r) + (int64_t)m * (k0 + tt)];
-                    if (r < nrj) b = F[(int64_t)(rj0 + r) + (int64_t)m * (k0 + tt)];
-                }
-                Pi[t][r] = -a;
-                Pj[t][r] = b;
+        __syncthreads();  // the previous item's readers are done with LDS
+        for (int e = threadIdx.x; e < ST * TB; e += NT) {
+            const int r = e % ST, t = e / ST;
+            double a = 0.0, b = 0.0;
+            if (t < kb) {
+                if (r < nri) a = F[(int64_t)(ri0 + r) + (int64_t)m * (k0 + t)];
+                if (r < nrj) b = F[(int64_t)(rj0 + r) + (int64_t)m * (k0 + t)];
             }
-            __syncthreads();
-            if (active) {
+            Pi[t][r] = -a;
+            Pj[t][r] = b;
+        }
+        __syncthreads();
+        if (active) {
+            for (int t0 = 0; t0 < TB; t0 += KC) {  // columns past kb are zero
 #pragma unroll
-                for (int t = 0; t < KC; t += 4) {
+                for (int t = t0; t < t0 + KC; t += 4) {
                     double av[4], bv[4];
 #pragma unroll
                     for (int a = 0; a < 4; a++) av[a] = Pi[t + lk][qr + 16 * a + li];
