@@ -436,6 +436,83 @@ constexpr int KC = 16;
 // a front's next-panel diagonal tile goes on to factor that panel's diagonal block, which it has just
 // brought up to date, into ldiag slot pslot[item] (-1: no such block), while the other work-groups are
 // still updating the rest: the diagonal-block Cholesky of step k+1 hides under the update of step k.
+// MFMA part of one tile: each wave computes a (16 RB) x (16 CB) block of the tile, the waves laid out as
+// (128 / 16 RB) x (cw / 16 CB); Pi, Pj hold the negated row panel and the column panel (64 columns,
+// zero past kb).  RB = CB = 4 for 128 x 128 tiles (2 x 2 waves), RB = 2, CB = 4 for the 128 x 64 tiles
+// of the next panel (4 x 1 waves, so the next panel's diagonal block is spread over two waves).
+template <int RB, int CB>
+__device__ __forceinline__ void tile_mma(double* __restrict__ F, int m, int ri0, int rj0, int nri, int nrj, int k0,
+                                         int kb, double* lds) {
+    const double(*Pi)[ST + 1] = reinterpret_cast<const double(*)[ST + 1]>(lds);
+    const double(*Pj)[ST + 1] = reinterpret_cast<const double(*)[ST + 1]>(lds + TB * (ST + 1));
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    constexpr int WR = ST / (16 * RB);  // waves along the rows
+    const int qr = (wave % WR) * 16 * RB, qc = (wave / WR) * 16 * CB;
+    const int li = lane % 16, lk = lane / 16;
+    // blocks outside the tile's columns or strictly above the diagonal do no MFMA work
+    const bool active = qc < nrj && ri0 + qr + 16 * RB - 1 >= rj0 + qc;
+    // D layout of the 16x16x4 f64 MFMA: item r of a lane is row (lane / 16) + 4 r, column lane % 16 of the
+    // product block; operands are swapped below so the block is C^T: C row = lane % 16, C column =
+    // (lane / 16) + 4 r (16 consecutive rows of a column per 16-lane group)
+    double4_t acc[RB][CB];
+#pragma unroll
+    for (int a = 0; a < RB; a++)
+#pragma unroll
+        for (int b = 0; b < CB; b++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int i = qr + 16 * a + li;
+                const int j = qc + 16 * b + lk + 4 * r;
+                const int gi = ri0 + i, gj = rj0 + j;
+                acc[a][b][r] = (active && i < nri && j < nrj && gi >= gj) ? F[(int64_t)gi + (int64_t)m * gj] : 0.0;
+            }
+    __syncthreads();  // the previous item's readers are done with LDS
+    for (int e = threadIdx.x; e < ST * TB; e += NT) {
+        const int r = e % ST, t = e / ST;
+        double av = 0.0, bv = 0.0;
+        if (t < kb) {
+            if (r < nri) av = F[(int64_t)(ri0 + r) + (int64_t)m * (k0 + t)];
+            if (r < nrj) bv = F[(int64_t)(rj0 + r) + (int64_t)m * (k0 + t)];
+        }
+        lds[t * (ST + 1) + r] = -av;
+        lds[TB * (ST + 1) + t * (ST + 1) + r] = bv;
+    }
+    __syncthreads();
+    if (active) {
+        for (int t0 = 0; t0 < TB; t0 += KC) {  // columns past kb are zero
+#pragma unroll
+            for (int t = t0; t < t0 + KC; t += 4) {
+                double av[RB], bv[CB];
+#pragma unroll
+                for (int a = 0; a < RB; a++) av[a] = Pi[t + lk][qr + 16 * a + li];
+#pragma unroll
+                for (int b = 0; b < CB; b++) bv[b] = Pj[t + lk][qc + 16 * b + li];
+#pragma unroll
+                for (int a = 0; a < RB; a++)
+#pragma unroll
+                    for (int b = 0; b < CB; b++)
+                        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[b], av[a], acc[a][b], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < RB; a++)
+#pragma unroll
+            for (int b = 0; b < CB; b++)
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const int i = qr + 16 * a + li;
+                    const int j = qc + 16 * b + lk + 4 * r;
+                    const int gi = ri0 + i, gj = rj0 + j;
+                    if (i < nri && j < nrj && gi >= gj) F[(int64_t)gi + (int64_t)m * gj] = acc[a][b][r];
+                }
+    }
+}
+
+// One launch per blocked step covers the whole trailing update: the first nnext items are 128 x 64 tiles of
+// the next panel's 64 columns, the rest 128 x 128 tiles of the columns after it.  The work-group holding
+// a front's next-panel diagonal tile goes on to factor that panel's diagonal block, which it has just
+// brought up to date, into ldiag slot pslot[item] (-1: no such block), while the other work-groups are
+// still updating the rest: the diagonal-block Cholesky of step k+1 hides under the update of step k.
 __global__ __launch_bounds__(NT) void blk_syrk(const int32_t* __restrict__ it, int nitems, int nnext,
                                                const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
                                                const int64_t* __restrict__ foff, double* __restrict__ fronts,
@@ -447,78 +524,17 @@ __global__ __launch_bounds__(NT) void blk_syrk(const int32_t* __restrict__ it, i
     // tile), reused by the fused diagonal-block Cholesky as its 64 x 64 column buffer
     __shared__ __attribute__((aligned(16))) double lds[2 * TB * (ST + 1)];
     __shared__ int badmin;
-    double(*Pi)[ST + 1] = reinterpret_cast<double(*)[ST + 1]>(lds);
-    double(*Pj)[ST + 1] = reinterpret_cast<double(*)[ST + 1]>(lds + TB * (ST + 1));
-    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-    const int qr = (wave / 2) * 64, qc = (wave % 2) * 64;
-    const int li = lane % 16, lk = lane / 16;
     for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
         const int s = it[4 * item], k0 = it[4 * item + 1];
         const int ri0 = it[4 * item + 2], rj0 = it[4 * item + 3];
-        const int cw = item < nnext ? TB : ST;
         const int m = mrows[s];
         const int kb = min(TB, ncol[s] - k0);
-        const int nri = min(ST, m - ri0), nrj = min(cw, m - rj0);
         double* F = fronts + foff[s];
-        // quadrants outside the tile's columns or strictly above the diagonal do no MFMA work
-        const bool active = qc < nrj && ri0 + qr + 63 >= rj0 + qc;
-        // D layout of the 16x16x4 f64 MFMA: item r of a lane is row (lane / 16) + 4 r, column lane % 16
-        // of the product block; operands are swapped below so the block is C^T: C row = lane % 16,
-        // C column = (lane / 16) + 4 r (16 consecutive rows of a column per 16-lane group)
-        double4_t acc[4][4];
-#pragma unroll
-        for (int a = 0; a < 4; a++)
-#pragma unroll
-            for (int b = 0; b < 4; b++)
-#pragma unroll
-                for (int r = 0; r < 4; r++) {
-                    const int i = qr + 16 * a + li;
-                    const int j = qc + 16 * b + lk + 4 * r;
-                    const int gi = ri0 + i, gj = rj0 + j;
-                    acc[a][b][r] = (active && i < nri && j < nrj && gi >= gj) ? F[(int64_t)gi + (int64_t)m * gj] : 0.0;
-                }
-        __syncthreads();  // the previous item's readers are done with LDS
-        for (int e = threadIdx.x; e < ST * TB; e += NT) {
-            const int r = e % ST, t = e / ST;
-            double a = 0.0, b = 0.0;
-            if (t < kb) {
-                if (r < nri) a = F[(int64_t)(ri0 + r) + (int64_t)m * (k0 + t)];
-                if (r < nrj) b = F[(int64_t)(rj0 + r) + (int64_t)m * (k0 + t)];
-            }
-            Pi[t][r] = -a;
-            Pj[t][r] = b;
-        }
-        __syncthreads();
-        if (active) {
-            for (int t0 = 0; t0 < TB; t0 += KC) {  // columns past kb are zero
-#pragma unroll
-                for (int t = t0; t < t0 + KC; t += 4) {
-                    double av[4], bv[4];
-#pragma unroll
-                    for (int a = 0; a < 4; a++) av[a] = Pi[t + lk][qr + 16 * a + li];
-#pragma unroll
-                    for (int b = 0; b < 4; b++) bv[b] = Pj[t + lk][qc + 16 * b + li];
-#pragma unroll
-                    for (int a = 0; a < 4; a++)
-#pragma unroll
-                        for (int b = 0; b < 4; b++)
-                            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[b], av[a], acc[a][b], 0, 0, 0);
-                }
-            }
-        }
-        if (active) {
-#pragma unroll
-            for (int a = 0; a < 4; a++)
-#pragma unroll
-                for (int b = 0; b < 4; b++)
-#pragma unroll
-                    for (int r = 0; r < 4; r++) {
-                        const int i = qr + 16 * a + li;
-                        const int j = qc + 16 * b + lk + 4 * r;
-                        const int gi = ri0 + i, gj = rj0 + j;
-                        if (i < nri && j < nrj && gi >= gj) F[(int64_t)gi + (int64_t)m * gj] = acc[a][b][r];
-                    }
-        }
+        const int nri = min(ST, m - ri0);
+        if (item < nnext)
+            tile_mma<2, 4>(F, m, ri0, rj0, nri, min(TB, m - rj0), k0, kb, lds);
+        else
+            tile_mma<4, 4>(F, m, ri0, rj0, nri, min(ST, m - rj0), k0, kb, lds);
         if (pslot && pslot[item] >= 0) {
             __syncthreads();  // the tile's stores are visible to the whole work-group; LDS is free
             potrf_block(s, rj0, pslot[item], first, ncol, mrows, foff, fronts, ldiag, rdiag, status, pr, lds,
