@@ -68,6 +68,8 @@ struct chol_sym {
     DBuf<int64_t> rel_off;
     DBuf<int32_t> rel;
     DBuf<int32_t> tile_sn, tile_rc;  // tile work list: supernode, (tr << 16) | tc
+    DBuf<int64_t> tile_cptr;         // per tile: its child rectangles in tile_crec
+    DBuf<int32_t> tile_crec;         // (child, ra, rb, ca, cb) per contributing child
     DBuf<int64_t> tile_kptr;
     DBuf<int32_t> tile_k, tile_kpos;
     DBuf<int32_t> lvl_sn_d, lvl_small_d, lvl_narrow_d, lvl_wide_d;
@@ -103,19 +105,11 @@ namespace {
 constexpr int TB = 64;      // tile edge
 constexpr int NT = 256;     // threads per work-group
 
-__device__ __forceinline__ int lower_bound_dev(const int32_t* a, int n, int v) {
-    int lo = 0, hi = n;
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (a[mid] < v)
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    return lo;
-}
 
 // ---------------------------------------------------------------- assembly
+// One work-group per 64 x 64 lower tile of a front: the tile is built in LDS from the entries of K that land
+// in it and from the rectangles of the children's update matrices that map into it (listed per tile at
+// analysis time, children in ascending order), then written to the front.  No atomics.
 __global__ __launch_bounds__(NT) void front_assemble(int tile0, const int32_t* __restrict__ tile_sn,
                                                      const int32_t* __restrict__ tile_rc,
                                                      const int64_t* __restrict__ tile_kptr,
@@ -124,8 +118,8 @@ __global__ __launch_bounds__(NT) void front_assemble(int tile0, const int32_t* _
                                                      const double* __restrict__ kval, const int32_t* __restrict__ ncol,
                                                      const int32_t* __restrict__ mrows,
                                                      const int64_t* __restrict__ foff,
-                                                     const int32_t* __restrict__ child_ptr,
-                                                     const int32_t* __restrict__ child,
+                                                     const int64_t* __restrict__ tile_cptr,
+                                                     const int32_t* __restrict__ tile_crec,
                                                      const int64_t* __restrict__ rel_off,
                                                      const int32_t* __restrict__ rel, double* __restrict__ fronts) {
     __shared__ double T[TB * TB];
@@ -138,15 +132,13 @@ __global__ __launch_bounds__(NT) void front_assemble(int tile0, const int32_t* _
     __syncthreads();
     for (int64_t e = tile_kptr[item] + threadIdx.x; e < tile_kptr[item + 1]; e += NT) T[tile_kpos[e]] = kval[tile_k[e]];
     __syncthreads();
-    for (int ci = child_ptr[s]; ci < child_ptr[s + 1]; ci++) {
-        const int c = child[ci];
+    for (int64_t q = tile_cptr[item]; q < tile_cptr[item + 1]; q++) {
+        const int32_t* rec = tile_crec + 5 * q;
+        const int c = rec[0], ra = rec[1], rb = rec[2], ca = rec[3], cb = rec[4];
         const int nc = ncol[c], mc = mrows[c];
-        const int nu = mc - nc;
         const int32_t* rl = rel + rel_off[c];
-        const int ra = lower_bound_dev(rl, nu, r0), rb = lower_bound_dev(rl, nu, r0 + TB);
-        const int ca = lower_bound_dev(rl, nu, c0), cb = lower_bound_dev(rl, nu, c0 + TB);
         const int nr = rb - ra, ncc = cb - ca;
-        if (nr > 0 && ncc > 0) {
+        {
             const double* F = fronts + foff[c];
             for (int e = threadIdx.x; e < nr * ncc; e += NT) {
                 const int ui = ra + e % nr, uj = ca + e / nr;
@@ -1010,6 +1002,53 @@ static void build_numeric_plan(chol_sym* C, const std::vector<int32_t>& colptr, 
             tkpos[q] = kpos[p];
         }
     }
+    // per tile: the children whose update matrices reach it, each with its row range [ra, rb) and column
+    // range [ca, cb) in the child's update-row numbering (relative indices are increasing, so each child
+    // contributes one rectangle per tile); children stay in ascending order, which fixes the summation order
+    std::vector<int64_t> tcptr(tsn.size() + 1, 0);
+    std::vector<int32_t> tcrec;  // 5 ints per entry: child, ra, rb, ca, cb
+    for (int pass = 0; pass < 2; pass++) {  // count, then fill
+        std::vector<int64_t> fill;
+        if (pass == 1) {
+            for (size_t t = 0; t < tsn.size(); t++) tcptr[t + 1] += tcptr[t];
+            tcrec.resize(5 * tcptr.back());
+            fill.assign(tcptr.begin(), tcptr.end() - 1);
+        }
+        std::vector<int32_t> lo;
+        for (int sp = 0; sp < ns; sp++) {
+            const int mp = C->h_mrows[sp], T = (mp + TB - 1) / TB;
+            for (int ci = cptr[sp]; ci < cptr[sp + 1]; ci++) {
+                const int c = clist[ci];
+                const int nu = C->h_mrows[c] - C->h_ncol[c];
+                const int32_t* rl = rel.data() + reloff[c];
+                // start of each row tile of the parent in the child's update rows
+                lo.assign(T + 1, nu);
+                for (int t = 0, u = 0; t <= T; t++) {
+                    while (u < nu && rl[u] < t * TB) u++;
+                    lo[t] = u;
+                }
+                for (int tc = 0; tc < T; tc++) {
+                    if (lo[tc + 1] == lo[tc]) continue;
+                    for (int tr = tc; tr < T; tr++) {
+                        if (lo[tr + 1] == lo[tr]) continue;
+                        // tiles of a front are ordered by column then row (tr >= tc)
+                        const int64_t tidx = tile_of_front_start[sp] + (int64_t)tc * T - (int64_t)tc * (tc - 1) / 2 +
+                                             (tr - tc);
+                        if (pass == 0) {
+                            tcptr[tidx + 1]++;
+                        } else {
+                            int32_t* r = tcrec.data() + 5 * fill[tidx]++;
+                            r[0] = c;
+                            r[1] = lo[tr];
+                            r[2] = lo[tr + 1];
+                            r[3] = lo[tc];
+                            r[4] = lo[tc + 1];
+                        }
+                    }
+                }
+            }
+        }
+    }
     // blocked-path work lists per level and step for fronts with m > 64
     std::vector<int32_t> pot, trs, syr, nslot;
     int max_slots = 0;
@@ -1121,6 +1160,8 @@ static void build_numeric_plan(chol_sym* C, const std::vector<int32_t>& colptr, 
     C->dev.upload(C->rel_off, reloff);
     C->dev.upload(C->rel, rel);
     C->dev.upload(C->tile_sn, tsn);
+    C->dev.upload(C->tile_cptr, tcptr);
+    C->dev.upload(C->tile_crec, tcrec);
     C->dev.upload(C->tile_rc, trc);
     C->dev.upload(C->tile_kptr, tkptr);
     C->dev.upload(C->tile_k, tk);
@@ -1278,7 +1319,7 @@ void chol_factor_enqueue(chol_sym* C, const double* kval, hipStream_t st, double
             tmark(C, st, 0);
             hipLaunchKernelGGL(front_assemble, dim3(t1 - t0), dim3(NT), 0, st, t0, C->tile_sn.p, C->tile_rc.p,
                                C->tile_kptr.p, C->tile_k.p, C->tile_kpos.p, kval, C->ncol.p, C->mrows.p, C->foff.p,
-                               C->child_ptr.p, C->child.p, C->rel_off.p, C->rel.p, C->fronts.p);
+                               C->tile_cptr.p, C->tile_crec.p, C->rel_off.p, C->rel.p, C->fronts.p);
             OPF_LAUNCH_CHECK();
             tmark(C, st, 0);
         }
