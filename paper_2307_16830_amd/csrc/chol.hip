@@ -47,6 +47,7 @@ struct chol_sym {
     std::vector<int32_t> lvl_ptr, lvl_sn;           // supernodes by level
     std::vector<int32_t> lvl_small_ptr, lvl_small;  // fronts with m <= 64 by level
     std::vector<int32_t> lvl_narrow_ptr, lvl_narrow;  // fronts solved by one work-group, by level
+    std::vector<int32_t> lvl_narrow_maxm;             // largest front of each level's list
     std::vector<int32_t> lvl_wide_ptr, lvl_wide;      // fronts with >= WIDE pivots, by level
     // assembly tile work list (per level)
     std::vector<int32_t> asm_ptr;                  // [nlevels+1] into tiles
@@ -548,8 +549,10 @@ __global__ void permute_out(int n, const int32_t* __restrict__ perm, const doubl
     if (k < n) x[perm[k]] = y[k];
 }
 
-// Forward sweep for one front: w = b(own rows) + children's partial results; solve with
-// the diagonal block; keep w on the off-diagonal rows as this front's partial result.
+// Forward sweep for one front: w = b(own rows) + children's partial results; solve with the diagonal
+// block; keep w on the off-diagonal rows as this front's partial result.  w lives in LDS (dynamic, wcap
+// doubles) when the front fits, else in the front's slice of `work`.  The gathers are unrolled by four so
+// that four independent index and value loads are in flight per thread.
 __global__ __launch_bounds__(NT) void solve_fwd(const int32_t* __restrict__ list, const int32_t* __restrict__ first,
                                                 const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
                                                 const int64_t* __restrict__ foff, const int64_t* __restrict__ roff,
@@ -558,10 +561,11 @@ __global__ __launch_bounds__(NT) void solve_fwd(const int32_t* __restrict__ list
                                                 const int32_t* __restrict__ child,
                                                 const int64_t* __restrict__ rel_off, const int32_t* __restrict__ rel,
                                                 const double* __restrict__ fronts, double* __restrict__ work,
-                                                double* __restrict__ upd, double* __restrict__ y) {
+                                                double* __restrict__ upd, double* __restrict__ y, int wcap) {
+    extern __shared__ double wl[];
     const int s = list[blockIdx.x];
     const int m = mrows[s], nn = ncol[s], f = first[s];
-    double* w = work + roff[s];
+    double* w = m <= wcap ? wl : work + roff[s];
     for (int t = threadIdx.x; t < m; t += NT) w[t] = t < nn ? y[f + t] : 0.0;
     __syncthreads();
     for (int ci = child_ptr[s]; ci < child_ptr[s + 1]; ci++) {
@@ -569,7 +573,16 @@ __global__ __launch_bounds__(NT) void solve_fwd(const int32_t* __restrict__ list
         const int nu = mrows[c] - ncol[c];
         const int32_t* rl = rel + rel_off[c];
         const double* uc = upd + uoff[c];
-        for (int t = threadIdx.x; t < nu; t += NT) w[rl[t]] += uc[t];
+        int t = threadIdx.x;
+        for (; t + 3 * NT < nu; t += 4 * NT) {
+            const int r0 = rl[t], r1 = rl[t + NT], r2 = rl[t + 2 * NT], r3 = rl[t + 3 * NT];
+            const double u0 = uc[t], u1 = uc[t + NT], u2 = uc[t + 2 * NT], u3 = uc[t + 3 * NT];
+            w[r0] += u0;
+            w[r1] += u1;
+            w[r2] += u2;
+            w[r3] += u3;
+        }
+        for (; t < nu; t += NT) w[rl[t]] += uc[t];
         __syncthreads();
     }
     const double* L = fronts + foff[s];
@@ -614,7 +627,15 @@ __global__ __launch_bounds__(NT) void solve_bwd(const int32_t* __restrict__ list
     for (int r0 = nn; r0 < m; r0 += XCH) {
         const int nr = min(XCH, m - r0);
         __syncthreads();
-        for (int t = threadIdx.x; t < nr; t += NT) xb[t] = y[R[r0 + t]];
+        int t = threadIdx.x;
+        for (; t + 3 * NT < nr; t += 4 * NT) {
+            const int i0 = R[r0 + t], i1 = R[r0 + t + NT], i2 = R[r0 + t + 2 * NT], i3 = R[r0 + t + 3 * NT];
+            xb[t] = y[i0];
+            xb[t + NT] = y[i1];
+            xb[t + 2 * NT] = y[i2];
+            xb[t + 3 * NT] = y[i3];
+        }
+        for (; t < nr; t += NT) xb[t] = y[R[r0 + t]];
         __syncthreads();
         for (int j = wv; j < nn; j += NT / 64) {
             const double* col = L + (int64_t)m * j + r0;
@@ -646,6 +667,7 @@ __global__ __launch_bounds__(NT) void solve_bwd(const int32_t* __restrict__ list
 // bounded: past the spin limit the fault word is raised and the work-group goes on (the result is then
 // invalid and reported).
 constexpr int WIDE = 256;  // fronts with at least this many pivots use the sync-free solves
+constexpr int WLDS = 8192; // rows of a narrow front's forward vector kept in LDS (64 KB)
 constexpr int SB = 64;     // block edge of the sync-free solves
 
 __device__ __forceinline__ void store_coherent(double* p, double v) {
@@ -932,6 +954,7 @@ static void build_numeric_plan(chol_sym* C, const std::vector<int32_t>& colptr, 
     C->lvl_small_ptr.assign(nl + 1, 0);
     C->lvl_small.clear();
     C->lvl_narrow_ptr.assign(nl + 1, 0);
+    C->lvl_narrow_maxm.clear();
     C->lvl_wide_ptr.assign(nl + 1, 0);
     C->lvl_narrow.clear();
     C->lvl_wide.clear();
@@ -941,6 +964,10 @@ static void build_numeric_plan(chol_sym* C, const std::vector<int32_t>& colptr, 
             (C->h_ncol[s] >= WIDE ? C->lvl_wide : C->lvl_narrow).push_back(s);
         }
         C->lvl_narrow_ptr[l + 1] = (int32_t)C->lvl_narrow.size();
+        int mx = 0;
+        for (int q = C->lvl_narrow_ptr[l]; q < C->lvl_narrow_ptr[l + 1]; q++)
+            mx = std::max(mx, C->h_mrows[C->lvl_narrow[q]]);
+        C->lvl_narrow_maxm.push_back(mx);
         C->lvl_wide_ptr[l + 1] = (int32_t)C->lvl_wide.size();
     }
     // assembly tiles and K entries per tile
@@ -1403,9 +1430,11 @@ void chol_solve_enqueue(chol_sym* C, const double* b, double* x, hipStream_t st)
     for (int l = 0; l < C->nlevels; l++) {
         int q0 = C->lvl_narrow_ptr[l], q1 = C->lvl_narrow_ptr[l + 1];
         if (q1 > q0) {
-            hipLaunchKernelGGL(solve_fwd, dim3(q1 - q0), dim3(NT), 0, st, C->lvl_narrow_d.p + q0, C->first.p,
-                               C->ncol.p, C->mrows.p, C->foff.p, C->roff.p, C->uoff.p, C->child_ptr.p, C->child.p,
-                               C->rel_off.p, C->rel.p, C->fronts.p, C->work.p, C->upd.p, y);
+            const int wcap = std::min(C->lvl_narrow_maxm[l], WLDS);  // fronts up to wcap rows keep w in LDS
+            hipLaunchKernelGGL(solve_fwd, dim3(q1 - q0), dim3(NT), (size_t)wcap * sizeof(double), st,
+                               C->lvl_narrow_d.p + q0, C->first.p, C->ncol.p, C->mrows.p, C->foff.p, C->roff.p,
+                               C->uoff.p, C->child_ptr.p, C->child.p, C->rel_off.p, C->rel.p, C->fronts.p,
+                               C->work.p, C->upd.p, y, wcap);
             OPF_LAUNCH_CHECK();
         }
         int w0 = C->lvl_wide_ptr[l], w1 = C->lvl_wide_ptr[l + 1];
