@@ -110,7 +110,10 @@ def main():
     stream = torch.cuda.current_stream()
     M = opf.Model(grid)
     t0 = time.perf_counter()
-    ipm = opf.IPM(M, tol=args.tol, max_iter=10000)
+    # at 80k buses exact minimum degree stops once the minimum degree reaches 1,500 (the rest, ~42.6k columns,
+    # is ordered by index into one dense front); below that the relative dense-tail rule alone applies
+    copts = opf.chol_options(dense_abs=1500) if args.config == "cfg3" else None
+    ipm = opf.IPM(M, tol=args.tol, max_iter=10000, chol_opts=copts)
     torch.cuda.synchronize()
     t_analyze = time.perf_counter() - t0
     C = ipm.chol()

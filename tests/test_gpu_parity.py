@@ -20,6 +20,12 @@ pytestmark = pytest.mark.gpu
 
 RTOL = 1e-12
 OPTS = dict(dense_frac=0.5, dense_abs=2 ** 31 - 1, max_width=2 ** 31 - 1, zero_abs=64, zero_rel=0.05)
+# 80k buses: minimum degree stops at degree 1,500 (a ~42.6k-column dense root), as in the benchmark
+OPTS_CFG3 = dict(OPTS, dense_abs=1500)
+
+
+def opts_for(case):
+    return OPTS_CFG3 if case == "cfg3" else OPTS
 
 
 def opf():
@@ -66,7 +72,7 @@ def assert_close(got, ref, mag, what):
 CASES = ["cfg0", (12, 16, 3, 5), "cfg1"]
 
 
-@pytest.mark.parametrize("case", CASES + ["cfg2"])
+@pytest.mark.parametrize("case", CASES + ["cfg2", "cfg3"])
 def test_derivatives_match_oracle(case):
     g = grid_for(case)
     g.gs[:] = np.linspace(0, 0.02, g.nbus)  # exercise the shunt terms of the balance rows
@@ -108,7 +114,7 @@ def _condensed_inputs(om, M, seed, dw):
     return x, y, sigx, D, dw
 
 
-@pytest.mark.parametrize("case", CASES + ["cfg2"])
+@pytest.mark.parametrize("case", CASES + ["cfg2", "cfg3"])
 def test_condensed_matrix_and_rhs_match_oracle(case):
     g = grid_for(case)
     M = opf().Model(g)
@@ -161,12 +167,12 @@ def _spd_system(case, seed=4):
     return M, kval
 
 
-@pytest.mark.parametrize("case", CASES + ["cfg2"])
+@pytest.mark.parametrize("case", CASES + ["cfg2", "cfg3"])
 def test_symbolic_analysis_bit_exact(case):
     M, _ = _spd_system(case)
     cp, ri = M.kkt_pattern()
-    C = opf().Cholesky(M.n, cp, ri, opf().chol_options(**OPTS))
-    sym = ochol.analyze(M.n, cp, ri, ochol.AnalyzeOptions(**OPTS))
+    C = opf().Cholesky(M.n, cp, ri, opf().chol_options(**opts_for(case)))
+    sym = ochol.analyze(M.n, cp, ri, ochol.AnalyzeOptions(**opts_for(case)))
     par, cc = C.etree()
     assert np.array_equal(C.perm(), sym.perm)
     assert np.array_equal(par, sym.parent)
@@ -207,11 +213,11 @@ def test_cholesky_factor_matches_oracle(case):
     assert np.max(np.abs(a - b) / scale) < 1e-10
 
 
-@pytest.mark.parametrize("case", CASES + ["cfg2"])
+@pytest.mark.parametrize("case", CASES + ["cfg2", "cfg3"])
 def test_solve_residual(case):
     M, kval = _spd_system(case)
     cp, ri = M.kkt_pattern()
-    C = opf().Cholesky(M.n, cp, ri, opf().chol_options(**OPTS))
+    C = opf().Cholesky(M.n, cp, ri, opf().chol_options(**opts_for(case)))
     assert C.factor(kval) == -1
     rng = np.random.default_rng(7)
     b = rng.normal(size=(2, M.n))
