@@ -419,6 +419,7 @@ __global__ __launch_bounds__(TR) void blk_trsm(const int32_t* __restrict__ it, c
 // the panel rows are staged through LDS in chunks of 16 columns.
 typedef double double4_t __attribute__((ext_vector_type(4)));
 constexpr int KC = 16;
+constexpr int KH = 32;  // panel columns staged in LDS at a time
 
 // Item: (front, k0, first row ri0, first column rj0) of a tile of up to 128 rows and cw columns.  The
 // accumulators start from the tile of C and the row panel is negated on its way into LDS, so the MFMAs
@@ -437,7 +438,7 @@ template <int RB, int CB>
 __device__ __forceinline__ void tile_mma(double* __restrict__ F, int m, int ri0, int rj0, int nri, int nrj, int k0,
                                          int kb, double* lds) {
     const double(*Pi)[ST + 1] = reinterpret_cast<const double(*)[ST + 1]>(lds);
-    const double(*Pj)[ST + 1] = reinterpret_cast<const double(*)[ST + 1]>(lds + TB * (ST + 1));
+    const double(*Pj)[ST + 1] = reinterpret_cast<const double(*)[ST + 1]>(lds + KH * (ST + 1));
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     constexpr int WR = ST / (16 * RB);  // waves along the rows
     const int qr = (wave % WR) * 16 * RB, qc = (wave / WR) * 16 * CB;
@@ -459,34 +460,41 @@ __device__ __forceinline__ void tile_mma(double* __restrict__ F, int m, int ri0,
                 const int gi = ri0 + i, gj = rj0 + j;
                 acc[a][b][r] = (active && i < nri && j < nrj && gi >= gj) ? F[(int64_t)gi + (int64_t)m * gj] : 0.0;
             }
-    __syncthreads();  // the previous item's readers are done with LDS
-    for (int e = threadIdx.x; e < ST * TB; e += NT) {
-        const int r = e % ST, t = e / ST;
-        double av = 0.0, bv = 0.0;
-        if (t < kb) {
-            if (r < nri) av = F[(int64_t)(ri0 + r) + (int64_t)m * (k0 + t)];
-            if (r < nrj) bv = F[(int64_t)(rj0 + r) + (int64_t)m * (k0 + t)];
+    // the panel slices go through LDS in halves of KH columns (columns past kb are zero; a half that starts
+    // at or past kb is skipped)
+    for (int h0 = 0; h0 < kb; h0 += KH) {
+        __syncthreads();  // earlier readers of LDS (this tile's previous half, or the previous item) are done
+        for (int e = threadIdx.x; e < ST * KH; e += NT) {
+            const int r = e % ST, t = e / ST;
+            double av = 0.0, bv = 0.0;
+            if (h0 + t < kb) {
+                if (r < nri) av = F[(int64_t)(ri0 + r) + (int64_t)m * (k0 + h0 + t)];
+                if (r < nrj) bv = F[(int64_t)(rj0 + r) + (int64_t)m * (k0 + h0 + t)];
+            }
+            lds[t * (ST + 1) + r] = -av;
+            lds[KH * (ST + 1) + t * (ST + 1) + r] = bv;
         }
-        lds[t * (ST + 1) + r] = -av;
-        lds[TB * (ST + 1) + t * (ST + 1) + r] = bv;
-    }
-    __syncthreads();
-    if (active) {
-        for (int t0 = 0; t0 < TB; t0 += KC) {  // columns past kb are zero
+        __syncthreads();
+        if (active) {
+#pragma unroll 2
+            for (int t0 = 0; t0 < KH; t0 += KC) {
 #pragma unroll
-            for (int t = t0; t < t0 + KC; t += 4) {
-                double av[RB], bv[CB];
+                for (int t = t0; t < t0 + KC; t += 4) {
+                    double av[RB], bv[CB];
 #pragma unroll
-                for (int a = 0; a < RB; a++) av[a] = Pi[t + lk][qr + 16 * a + li];
+                    for (int a = 0; a < RB; a++) av[a] = Pi[t + lk][qr + 16 * a + li];
 #pragma unroll
-                for (int b = 0; b < CB; b++) bv[b] = Pj[t + lk][qc + 16 * b + li];
+                    for (int b = 0; b < CB; b++) bv[b] = Pj[t + lk][qc + 16 * b + li];
 #pragma unroll
-                for (int a = 0; a < RB; a++)
+                    for (int a = 0; a < RB; a++)
 #pragma unroll
-                    for (int b = 0; b < CB; b++)
-                        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[b], av[a], acc[a][b], 0, 0, 0);
+                        for (int b = 0; b < CB; b++)
+                            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[b], av[a], acc[a][b], 0, 0, 0);
+                }
             }
         }
+    }
+    if (active) {
 #pragma unroll
         for (int a = 0; a < RB; a++)
 #pragma unroll
@@ -506,16 +514,18 @@ __device__ __forceinline__ void tile_mma(double* __restrict__ F, int m, int ri0,
 // a front's next-panel diagonal tile goes on to factor that panel's diagonal block, which it has just
 // brought up to date, into ldiag slot pslot[item] (-1: no such block), while the other work-groups are
 // still updating the rest: the diagonal-block Cholesky of step k+1 hides under the update of step k.
-__global__ __launch_bounds__(NT) void blk_syrk(const int32_t* __restrict__ it, int nitems, int nnext,
+__global__ __launch_bounds__(NT, 2) void blk_syrk(const int32_t* __restrict__ it, int nitems, int nnext,
                                                const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
                                                const int64_t* __restrict__ foff, double* __restrict__ fronts,
                                                const int32_t* __restrict__ pslot,
                                                const int32_t* __restrict__ first, double* __restrict__ ldiag,
                                                double* __restrict__ rdiag, int32_t* __restrict__ status,
                                                PivotRef pr) {
-    // LDS: both 64-column panel slices of the tile at once (132 KB, so one load phase and one barrier per
-    // tile), reused by the fused diagonal-block Cholesky as its 64 x 64 column buffer
-    __shared__ __attribute__((aligned(16))) double lds[2 * TB * (ST + 1)];
+    // LDS: both panel slices of the tile, KH columns at a time (66 KB, so two work-groups share a compute
+    // unit and one's loads overlap the other's MFMAs), reused by the fused diagonal-block Cholesky as its
+    // 64 x 64 column buffer
+    __shared__ __attribute__((aligned(16))) double lds[2 * KH * (ST + 1)];
+    static_assert(2 * KH * (ST + 1) >= TB * TB, "the column buffer of the diagonal-block Cholesky fits");
     __shared__ int badmin;
     for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
         const int s = it[4 * item], k0 = it[4 * item + 1];
@@ -1482,6 +1492,9 @@ void chol_solve_enqueue(chol_sym* C, const double* b, double* x, hipStream_t st)
 }
 
 // Raised by a sync-free solve whose wait exceeded its bound (the solve result is invalid).
+// The analysis's device buffers and uploads, normally performed at the first factorization, done now.
+void chol_prepare_device(chol_sym* C) { C->dev.run(); }
+
 int chol_solve_fault(chol_sym* C, hipStream_t st) {
     if (C->h_flag_off.empty()) return 0;
     int32_t v = 0;
