@@ -58,6 +58,85 @@ def recorded_traffic():
     return float(t.group(1))
 
 
+def _trace_grid(req):
+    from paper_2307_16830_amd import gridgen
+    seed, nb, ne, ng, lf = req
+    return seed, gridgen.make_grid(nb, ne, ng, seed, load_factor=lf)
+
+
+def serving_grids(nreq):
+    """The first ``nreq`` requests of the serving trace (log-uniform 30..2,000 buses), generated on host
+    processes; called before the GPU is touched."""
+    import multiprocessing as mp
+    from paper_2307_16830_amd import gridgen
+    trace = gridgen.serving_trace(512)[:nreq]
+    with mp.get_context("fork").Pool(min(8, os.cpu_count() or 1)) as pool:
+        return pool.map(_trace_grid, trace)
+
+
+def pct(v, q):
+    return float(np.percentile(np.asarray(v), q)) if len(v) else None
+
+
+def serving_bench(grids, slots, rate_factor):
+    """Continuous-batching server vs one-at-a-time solves on the same GPU and the same requests.
+
+    The one-at-a-time path creates, analyzes and solves each request alone on one stream; its service times
+    give the sequential rate.  Arrivals are Poisson at ``rate_factor`` times that rate (SplitMix64 draws);
+    the server gets each request at its arrival time, and the sequential path's latencies on the same
+    arrivals follow from its service times (first come, first served)."""
+    import torch
+    from paper_2307_16830_amd import gridgen, opf
+
+    def alone(g):
+        M = opf.Model(g)
+        ipm = opf.IPM(M, tol=1e-4, max_iter=500)
+        rc, it, obj = ipm.solve()
+        torch.cuda.synchronize()
+        return rc
+
+    alone(grids[0][1])  # warm-up (first launches of every kernel)
+    service, conv_seq = [], 0
+    for tag, g in grids:
+        t0 = time.perf_counter()
+        conv_seq += alone(g) == opf.OK
+        service.append(time.perf_counter() - t0)
+    seq_rate = len(grids) / sum(service)
+    u = gridgen.SplitMix64(4).uniform(len(grids))
+    arrive = np.cumsum(-np.log1p(-u) / (rate_factor * seq_rate))
+    lat_seq, t_free = [], 0.0
+    for a, sv in zip(arrive, service):
+        t_free = max(a, t_free) + sv
+        lat_seq.append(t_free - a)
+    srv = opf.Server(slots=slots, hbm_budget=8 << 30)
+    t0 = srv.now()
+    for k, (tag, g) in enumerate(grids):
+        while srv.now() - t0 < arrive[k]:
+            time.sleep(2e-4)
+        srv.submit(g, tag)
+    res = {}
+    while len(res) < len(grids):
+        got = srv.poll(wait=True)
+        if not got:
+            raise RuntimeError("server went idle with results missing")
+        for r in got:
+            res[r["tag"]] = r
+    st = srv.stats()
+    srv.close()
+    lat = [r["t_done"] - r["t_submit"] for r in res.values()]
+    makespan = max(r["t_done"] for r in res.values()) - t0
+    return {
+        "requests": len(grids), "slots": slots,
+        "workload": "serving trace: seeded grids, buses log-uniform on [30, 2000], loads x U(0.9, 1.1), tol 1e-4",
+        "arrivals": f"Poisson at {rate_factor}x the sequential solve rate",
+        "solves_per_s": len(grids) / makespan, "p50_ms": 1e3 * pct(lat, 50), "p99_ms": 1e3 * pct(lat, 99),
+        "converged": sum(r["status"] == 1 for r in res.values()),
+        "peak_pool_bytes": st["peak_in_use"],
+        "sequential": {"solves_per_s": seq_rate, "p50_ms": 1e3 * pct(lat_seq, 50), "p99_ms": 1e3 * pct(lat_seq, 99),
+                       "converged": conv_seq},
+    }
+
+
 def cpu_baseline(grid, budget_s):
     """The oracle (plain CPU reference) timed on one IPM iteration of the same grid, analysis excluded."""
     from oracle import ipm as oipm
@@ -82,6 +161,11 @@ def main():
     ap.add_argument("--config", default="cfg2")
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving", type=int, default=32, metavar="REQUESTS",
+                    help="also run this many requests of the serving trace through the batched server and one at "
+                         "a time (0: skip)")
+    ap.add_argument("--serving-slots", type=int, default=4)
+    ap.add_argument("--serving-rate", type=float, default=1.5)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of this many MiB (a reference kernel of known "
                          "traffic for hardware-counter runs)")
@@ -90,6 +174,7 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
         sys.exit(2)
 
+    sgrids = serving_grids(args.serving) if args.serving > 0 else None  # host work, before the GPU is touched
     import torch
     from paper_2307_16830_amd import gridgen, opf
 
@@ -193,6 +278,11 @@ def main():
         "factorization_tflops": factor_tflops,
         "factor_kernels_ms_per_iter": {k: v["ms"] / 2 for k, v in kt_all.items()},
     }
+    del ipm, C, M
+    if sgrids:
+        log(f"[bench] serving: {len(sgrids)} requests, {args.serving_slots} slots")
+        out["serving"] = serving_bench(sgrids, args.serving_slots, args.serving_rate)
+        log(f"[bench] serving: {out['serving']}")
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on one iteration of the same grid")
         out["cpu_baseline"] = cpu_baseline(grid, 30.0)

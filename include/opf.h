@@ -37,7 +37,8 @@ typedef enum {
     OPF_E_NOT_PD = -5,     /* non-positive pivot in the Cholesky factorization */
     OPF_E_MAXITER = -6,    /* IPM iteration limit reached */
     OPF_E_LINESEARCH = -7, /* filter line search could not find an acceptable step */
-    OPF_E_NUMERIC = -8     /* NaN/Inf in an iterate or a residual */
+    OPF_E_NUMERIC = -8,    /* NaN/Inf in an iterate or a residual */
+    OPF_E_BUDGET = -9      /* a served request needs more HBM than the server's whole pool */
 } opf_status;
 
 const char* opf_last_error(void);
@@ -265,6 +266,67 @@ int ipm_set_state(ipm_state* state, const double* x, const double* s, const doub
  * regularization and refinement steps used. */
 int ipm_direction(ipm_state* state, double* dx, double* ds, double* dy, double* dzl, double* dzu, double* dvl,
                   double* dvu, double* delta_w, int32_t* ir_steps);
+
+/* ----------------------------------------------------------------------
+ * Continuous-batching solve server (serving many ACOPF instances at once).
+ *
+ * The paper solves one instance at a time; this server keeps several solves
+ * on the device together.  Requests (grids) arrive at any time through
+ * opf_serve_submit.  A request is admitted when one of the server's worker
+ * slots is free and its device footprint fits in the server's HBM pool: the
+ * slot creates the request's model and IPM state (analysis on the host, all
+ * device buffers carved from one region of the pool, whose size is the
+ * request's exact footprint) and then runs the whole IPM (Algorithm 1) on the
+ * slot's own HIP stream, so the work of admitted requests overlaps on the
+ * device.  When a solve ends its region returns to the pool and the next
+ * waiting request is admitted.  A request never shares a buffer with another,
+ * so its result does not depend on what else is in flight.
+ *
+ * Ownership: the grid is copied at submission (the caller may free it after
+ * the call returns).  Results stay in the server until taken with
+ * opf_serve_poll / opf_serve_get_x.  The pool is one device allocation made
+ * by opf_serve_create and freed by opf_serve_destroy.  A server is safe to
+ * use from one host thread at a time (its workers are internal threads).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int32_t slots;        /* worker slots = requests on the device at once (default 4, at most 64) */
+    int64_t hbm_budget;   /* bytes of the device pool (default 8 GiB) */
+    ipm_options ipm;      /* options of every solve (defaults of ipm_default_options) */
+    chol_options chol;    /* analysis options of every solve (defaults of chol_default_options) */
+} serve_options;
+
+typedef struct {
+    int64_t tag;          /* the caller's tag from opf_serve_submit */
+    int32_t status;       /* final status of the solve: 1 converged, or a negative opf_status */
+    int32_t iterations;
+    double objective;     /* unscaled objective at the final iterate */
+    int32_t n, m;         /* variables and rows of the request's model */
+    int64_t footprint;    /* device bytes the request held while admitted */
+    double t_submit, t_admit, t_done;  /* host steady-clock seconds (same clock as opf_serve_now) */
+} serve_result;
+
+typedef struct opf_server opf_server;
+
+void serve_default_options(serve_options* o);
+/* Allocates the pool and starts the workers on the current device. */
+int opf_serve_create(const serve_options* o, opf_server** out);
+/* Queue one request.  The model's host structure is built here (OPF_E_INVALID
+ * for a bad grid); admission and the solve happen on a worker. */
+int opf_serve_submit(opf_server* srv, const opf_grid* grid, int64_t tag);
+/* Up to ``max`` finished results (oldest first) into ``out``; *count receives
+ * how many.  With wait != 0 the call blocks until at least one is ready or
+ * nothing is queued or running. */
+int opf_serve_poll(opf_server* srv, serve_result* out, int32_t max, int32_t* count, int32_t wait);
+/* Host copy of the final iterate x [n] of a finished request (any time before
+ * opf_serve_destroy); OPF_E_INVALID for an unknown tag or a wrong n. */
+int opf_serve_get_x(opf_server* srv, int64_t tag, double* x, int32_t n);
+/* Pool statistics: bytes in use now and the largest in use at once. */
+int opf_serve_stats(const opf_server* srv, int64_t* in_use, int64_t* peak_in_use, int32_t* running,
+                    int32_t* queued);
+/* Seconds on the server's steady clock. */
+double opf_serve_now(void);
+/* Waits for every queued and running request, stops the workers, frees the pool. */
+int opf_serve_destroy(opf_server* srv);
 
 #ifdef __cplusplus
 }

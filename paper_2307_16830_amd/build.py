@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libopf.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["model.hip", "kkt.hip", "chol.hip", "ipm.hip", "symbolic.cpp"]
+SOURCES = ["model.hip", "kkt.hip", "chol.hip", "ipm.hip", "serve.hip", "symbolic.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-result",

@@ -57,26 +57,41 @@ int guarded(F&& f) {
     }
 }
 
+// A slice of device memory that buffers of the calling host thread are carved from instead of hipMalloc
+// (bump allocation, 256-byte aligned, nothing freed individually).  The solve server installs one per request
+// while it creates that request's model and IPM state, so that admission can count the request's exact
+// footprint and the request's memory comes from the server's pool without device-synchronizing frees.
+struct DeviceRegion {
+    char* base = nullptr;
+    size_t cap = 0;
+    size_t used = 0;
+};
+DeviceRegion*& thread_region();  // the calling thread's region, or nullptr (plain hipMalloc)
+
 // Owning HBM buffer.
 template <class T>
 struct DBuf {
     T* p = nullptr;
     size_t n = 0;
+    bool pooled = false;  // carved from a DeviceRegion: not freed individually
     DBuf() = default;
     explicit DBuf(size_t count) { alloc(count); }
     DBuf(const DBuf&) = delete;
     DBuf& operator=(const DBuf&) = delete;
-    DBuf(DBuf&& o) noexcept : p(o.p), n(o.n) {
+    DBuf(DBuf&& o) noexcept : p(o.p), n(o.n), pooled(o.pooled) {
         o.p = nullptr;
         o.n = 0;
+        o.pooled = false;
     }
     DBuf& operator=(DBuf&& o) noexcept {
         if (this != &o) {
             release();
             p = o.p;
             n = o.n;
+            pooled = o.pooled;
             o.p = nullptr;
             o.n = 0;
+            o.pooled = false;
         }
         return *this;
     }
@@ -85,6 +100,18 @@ struct DBuf {
         release();
         n = count;
         if (count == 0) return;
+        if (DeviceRegion* r = thread_region()) {
+            const size_t off = (r->used + 255) & ~size_t(255), bytes = count * sizeof(T);
+            if (off > r->cap || bytes > r->cap - off) {
+                n = 0;
+                set_error("device region of %zu bytes exhausted (%zu used, %zu more requested)", r->cap, off, bytes);
+                throw Error{OPF_E_NOMEM};
+            }
+            p = reinterpret_cast<T*>(r->base + off);
+            r->used = off + bytes;
+            pooled = true;
+            return;
+        }
         hipError_t e = hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T));
         if (e != hipSuccess) {
             p = nullptr;
@@ -94,9 +121,10 @@ struct DBuf {
         }
     }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p && !pooled) (void)hipFree(p);
         p = nullptr;
         n = 0;
+        pooled = false;
     }
     void upload(const std::vector<T>& h, hipStream_t s = nullptr) {
         alloc(h.size());

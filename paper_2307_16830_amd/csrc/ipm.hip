@@ -26,6 +26,7 @@ void chol_factor_enqueue(chol_sym* C, const double* kval, hipStream_t st, double
 int chol_factor_sync(chol_sym* C, const double* kval, hipStream_t st, double pivot_tol);
 void chol_solve_enqueue(chol_sym* C, const double* b, double* x, hipStream_t st);
 int chol_solve_fault(chol_sym* C, hipStream_t st);
+void chol_prepare_device(chol_sym* C);
 }  // namespace opf
 
 using namespace opf;
@@ -683,6 +684,16 @@ extern "C" int ipm_destroy(ipm_state* S) {
 }
 
 extern "C" chol_sym* ipm_chol(ipm_state* S) { return S ? S->C : nullptr; }
+
+// Every device buffer of a state allocated and uploaded now (the analysis's normally wait for the first
+// factorization); used by the solve server to count a request's footprint at admission.
+int ipm_prepare_device(ipm_state* S) {
+    return guarded([&] {
+        OPF_CHECK(S, OPF_E_INVALID, "ipm_prepare_device: null state");
+        chol_prepare_device(S->C);
+        OPF_HIP(hipStreamSynchronize(S->st));
+    });
+}
 
 // Newton direction at the current iterate for barrier parameter mu: Hessian,
 // residuals, diagonals, factorization with inertia correction (primal

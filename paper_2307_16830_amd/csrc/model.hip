@@ -21,6 +21,11 @@ namespace opf {
 
 static thread_local char g_err[1024] = "";
 
+DeviceRegion*& thread_region() {
+    static thread_local DeviceRegion* r = nullptr;
+    return r;
+}
+
 void set_error(const char* fmt, ...) {
     va_list ap;
     va_start(ap, fmt);

@@ -245,6 +245,26 @@ def _cg(A, b):
     return sol if info == 0 else None
 
 
+DIRECT_MAX = 5000  # reduced susceptance systems up to this size are solved by sparse LU, larger ones by CG
+
+
+def _solver(A):
+    """Solve function for repeated right-hand sides with the SPD matrix A (None where it fails)."""
+    if A.shape[0] <= DIRECT_MAX:
+        import scipy.sparse.linalg as spla
+
+        try:
+            lu = spla.splu(A.tocsc())
+        except RuntimeError:
+            return lambda b: None
+
+        def solve(b):
+            x = lu.solve(np.asarray(b, dtype=np.float64))
+            return x if np.all(np.isfinite(x)) else None
+        return solve
+    return lambda b: _cg(A, b)
+
+
 def _ac_power_flow(N, fr, to, r, x, bch, bs, gbus, pgen_k, pd, qd, vset, max_iter=400):
     """Fast-decoupled AC power flow (Stott & Alsac, 1974) in complex bus-admittance form.
 
@@ -278,6 +298,8 @@ def _ac_power_flow(N, fr, to, r, x, bch, bs, gbus, pgen_k, pd, qd, vset, max_ite
                         (np.concatenate([fr, to, fr, to]), np.concatenate([fr, to, to, fr]))), shape=(N, N))
     Bp = Bp[nsl][:, nsl].tocsr()
     Bpp = (-Y.imag)[ipq][:, ipq].tocsr()
+    solve_p = _solver(Bp)
+    solve_q = _solver(Bpp) if len(ipq) else None
     for _ in range(max_iter):
         V = vm * np.exp(1j * th)
         S = V * np.conj(Y @ V)
@@ -288,7 +310,7 @@ def _ac_power_flow(N, fr, to, r, x, bch, bs, gbus, pgen_k, pd, qd, vset, max_ite
             return V, S
         if not np.isfinite(mis) or mis > 1e3 or np.min(vm) < 0.5:
             return None
-        dth = _cg(Bp, dP[nsl] / vm[nsl])
+        dth = solve_p(dP[nsl] / vm[nsl])
         if dth is None:
             return None
         th[nsl] += dth
@@ -296,7 +318,7 @@ def _ac_power_flow(N, fr, to, r, x, bch, bs, gbus, pgen_k, pd, qd, vset, max_ite
             V = vm * np.exp(1j * th)
             S = V * np.conj(Y @ V)
             dQ = qsp - S.imag
-            dv = _cg(Bpp, dQ[ipq] / vm[ipq])
+            dv = solve_q(dQ[ipq] / vm[ipq])
             if dv is None:
                 return None
             vm[ipq] += dv
@@ -403,11 +425,12 @@ def _feasibility_repair(N, fr, to, r, x, bch, gbus, pmax, qmin, qmax, rate, pd):
                                (np.concatenate([fr, to, fr, to, np.arange(N)]),
                                 np.concatenate([fr, to, to, fr, np.arange(N)]))), shape=(N, N))
             Bpp = (-Y.imag)[ipq][:, ipq].tocsr()
+            solve_t = _solver(Bpp)
             nb = bs.copy()
             for i in np.flatnonzero(st["vbad"] | ((~isgen) & ((vm < 0.955) | (vm > 1.045)))):
                 e = np.zeros(len(ipq))
                 e[pos[i]] = 1.0
-                t = _cg(Bpp, e)
+                t = solve_t(e)
                 if t is None or t[pos[i]] <= 0:
                     continue
                 nb[i] += float(np.clip(0.5 * (1.0 - vm[i]) / (t[pos[i]] * vm[i] ** 2), -0.05, 0.05))

@@ -21,8 +21,8 @@ I64P = ctypes.POINTER(ctypes.c_int64)
 F64P = ctypes.POINTER(ctypes.c_double)
 VP = ctypes.c_void_p
 
-OK, E_INVALID, E_NOMEM, E_DEVICE, E_STATE, E_NOT_PD, E_MAXITER, E_LINESEARCH, E_NUMERIC = 0, -1, -2, -3, -4, -5, -6, \
-    -7, -8
+OK, E_INVALID, E_NOMEM, E_DEVICE, E_STATE, E_NOT_PD, E_MAXITER, E_LINESEARCH, E_NUMERIC, E_BUDGET = \
+    0, -1, -2, -3, -4, -5, -6, -7, -8, -9
 EVAL_F, EVAL_C, EVAL_GRAD, EVAL_JAC, EVAL_HESS = 1, 2, 4, 8, 16
 EXPORTED = [
     "opf_last_error", "opf_create", "opf_destroy", "opf_dims", "opf_structure", "opf_bounds", "opf_initial_point",
@@ -30,7 +30,8 @@ EXPORTED = [
     "chol_info", "chol_perm", "chol_etree", "chol_supernodes", "chol_supernode_rows", "chol_factor", "chol_solve",
     "chol_export_factor", "ipm_default_options", "ipm_create", "ipm_destroy", "ipm_step", "ipm_solve",
     "ipm_get_iterate", "ipm_chol", "ipm_get_state", "ipm_set_state", "ipm_direction", "chol_timing",
-    "chol_timing_read",
+    "chol_timing_read", "serve_default_options", "opf_serve_create", "opf_serve_submit", "opf_serve_poll",
+    "opf_serve_get_x", "opf_serve_stats", "opf_serve_now", "opf_serve_destroy",
 ]
 
 
@@ -57,6 +58,21 @@ class IpmOptions(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("max_ir", ctypes.c_int32),
                 ("ir_tol", ctypes.c_double), ("mu_init", ctypes.c_double), ("bound_relax", ctypes.c_double),
                 ("pivot_tol", ctypes.c_double)]
+
+
+class ServeOptions(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int32), ("hbm_budget", ctypes.c_int64), ("ipm", IpmOptions),
+                ("chol", CholOptions)]
+
+
+class ServeResult(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_int64), ("status", ctypes.c_int32), ("iterations", ctypes.c_int32),
+                ("objective", ctypes.c_double), ("n", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("footprint", ctypes.c_int64), ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class IterInfo(ctypes.Structure):
@@ -115,6 +131,16 @@ def lib():
         L.ipm_get_state.argtypes = [VP] + [F64P] * 9
         L.ipm_set_state.argtypes = [VP] + [F64P] * 7 + [ctypes.c_double, ctypes.c_double]
         L.ipm_direction.argtypes = [VP] + [F64P] * 8 + [I32P]
+        L.serve_default_options.argtypes = [ctypes.POINTER(ServeOptions)]
+        L.serve_default_options.restype = None
+        L.opf_serve_create.argtypes = [ctypes.POINTER(ServeOptions), ctypes.POINTER(VP)]
+        L.opf_serve_submit.argtypes = [VP, ctypes.POINTER(GridC), ctypes.c_int64]
+        L.opf_serve_poll.argtypes = [VP, ctypes.POINTER(ServeResult), ctypes.c_int32, I32P, ctypes.c_int32]
+        L.opf_serve_get_x.argtypes = [VP, ctypes.c_int64, F64P, ctypes.c_int32]
+        L.opf_serve_stats.argtypes = [VP, I64P, I64P, I32P, I32P]
+        L.opf_serve_now.argtypes = []
+        L.opf_serve_now.restype = ctypes.c_double
+        L.opf_serve_destroy.argtypes = [VP]
         _lib = L
     return _lib
 
@@ -160,23 +186,29 @@ def ipm_options(**kw):
     return o
 
 
+def _grid_struct(grid, keep):
+    """opf_grid view of a generated grid; ``keep`` holds the arrays alive while the struct is used."""
+    g = GridC()
+    g.nbus, g.nbranch, g.ngen = grid.nbus, grid.nbranch, grid.ngen
+    g.ref_bus, g.base_mva = int(grid.ref_bus), float(grid.base_mva)
+    for k in ("pd", "qd", "gs", "bs", "vmin", "vmax", "r", "x", "b", "rate", "angmin", "angmax",
+              "c2", "c1", "c0", "pmin", "pmax", "qmin", "qmax"):
+        a = np.ascontiguousarray(getattr(grid, k), dtype=np.float64)
+        keep[k] = a
+        setattr(g, k, _p(a, F64P))
+    for k in ("f", "t", "gbus"):
+        a = np.ascontiguousarray(getattr(grid, k), dtype=np.int32)
+        keep[k] = a
+        setattr(g, k, _p(a, I32P))
+    return g
+
+
 class Model:
     """An ACOPF instance on the device (wraps ``opf_model``)."""
 
     def __init__(self, grid):
         self._keep = {}
-        g = GridC()
-        g.nbus, g.nbranch, g.ngen = grid.nbus, grid.nbranch, grid.ngen
-        g.ref_bus, g.base_mva = int(grid.ref_bus), float(grid.base_mva)
-        for k in ("pd", "qd", "gs", "bs", "vmin", "vmax", "r", "x", "b", "rate", "angmin", "angmax",
-                  "c2", "c1", "c0", "pmin", "pmax", "qmin", "qmax"):
-            a = np.ascontiguousarray(getattr(grid, k), dtype=np.float64)
-            self._keep[k] = a
-            setattr(g, k, _p(a, F64P))
-        for k in ("f", "t", "gbus"):
-            a = np.ascontiguousarray(getattr(grid, k), dtype=np.int32)
-            self._keep[k] = a
-            setattr(g, k, _p(a, I32P))
+        g = _grid_struct(grid, self._keep)
         h = VP()
         _check(lib().opf_create(ctypes.byref(g), ctypes.byref(h)), "opf_create")
         self._h = h
@@ -403,7 +435,65 @@ class IPM:
 def status_name(rc):
     return {OK: "OK", 1: "CONVERGED", E_INVALID: "E_INVALID", E_NOMEM: "E_NOMEM", E_DEVICE: "E_DEVICE",
             E_STATE: "E_STATE", E_NOT_PD: "E_NOT_PD", E_MAXITER: "E_MAXITER", E_LINESEARCH: "E_LINESEARCH",
-            E_NUMERIC: "E_NUMERIC"}.get(rc, str(rc))
+            E_NUMERIC: "E_NUMERIC", E_BUDGET: "E_BUDGET"}.get(rc, str(rc))
+
+
+def serve_options(slots=4, hbm_budget=8 << 30, tol=1e-4, max_iter=500, chol_opts=None, **ipm_kw):
+    o = ServeOptions()
+    lib().serve_default_options(ctypes.byref(o))
+    o.slots, o.hbm_budget = int(slots), int(hbm_budget)
+    o.ipm.tol, o.ipm.max_iter = float(tol), int(max_iter)
+    for k, v in ipm_kw.items():
+        setattr(o.ipm, k, v)
+    if chol_opts is not None:
+        o.chol = chol_opts
+    return o
+
+
+class Server:
+    """Continuous-batching ACOPF solve server (wraps ``opf_server``): submit grids at any time; each is
+    admitted by device footprint into a worker slot and solved on that slot's stream."""
+
+    def __init__(self, **kw):
+        h = VP()
+        _check(lib().opf_serve_create(ctypes.byref(serve_options(**kw)), ctypes.byref(h)), "opf_serve_create")
+        self._h = h
+
+    def submit(self, grid, tag):
+        keep = {}
+        g = _grid_struct(grid, keep)
+        _check(lib().opf_serve_submit(self._h, ctypes.byref(g), int(tag)), "opf_serve_submit")
+
+    def poll(self, wait=True, max_results=64):
+        """Finished results (dicts, oldest first); with ``wait`` blocks until one is ready or all is done."""
+        buf = (ServeResult * max_results)()
+        cnt = ctypes.c_int32()
+        _check(lib().opf_serve_poll(self._h, buf, max_results, ctypes.byref(cnt), 1 if wait else 0),
+               "opf_serve_poll")
+        return [buf[i].as_dict() for i in range(cnt.value)]
+
+    def x(self, tag, n):
+        out = np.empty(n)
+        _check(lib().opf_serve_get_x(self._h, int(tag), _p(out, F64P), int(n)), "opf_serve_get_x")
+        return out
+
+    def stats(self):
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        c, d = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().opf_serve_stats(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d)),
+               "opf_serve_stats")
+        return {"in_use": a.value, "peak_in_use": b.value, "running": c.value, "queued": d.value}
+
+    @staticmethod
+    def now():
+        return lib().opf_serve_now()
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.opf_serve_destroy(self._h)
+        self._h = None
+
+    __del__ = close
 
 
 INF = math.inf
