@@ -1,6 +1,7 @@
 """CPU-side checks of the C-ABI library: it loads, exports every declared symbol, and its host logic
 (structure, bounds, condensed pattern, symbolic analysis) is bit-exact with the oracle.  No device
 compute is called: device uploads are deferred to the first device use."""
+import ctypes
 import os
 import re
 
@@ -107,3 +108,20 @@ def test_chol_analyze_rejects_bad_patterns():
         O.Cholesky(3, np.array([0, 1, 2, 2]), np.array([0, 1]))  # column 2 lacks its diagonal
     with pytest.raises(O.OpfError):
         O.Cholesky(2, np.array([0, 1, 2]), np.array([1, 1]))  # entry above the diagonal
+
+
+def test_serving_defaults_and_argument_checks():
+    O = opf()
+    o = O.ServeOptions()
+    O.lib().serve_default_options(ctypes.byref(o))
+    assert o.slots == 4 and o.hbm_budget == 8 << 30
+    assert o.ipm.tol == 1e-4 and o.chol.dense_frac == 0.5
+    # argument errors are reported before any device work
+    h = ctypes.c_void_p()
+    bad = O.ServeOptions()
+    O.lib().serve_default_options(ctypes.byref(bad))
+    bad.slots = 0
+    assert O.lib().opf_serve_create(ctypes.byref(bad), ctypes.byref(h)) == O.E_INVALID
+    assert O.lib().opf_serve_submit(None, None, 0) == O.E_INVALID
+    assert O.lib().opf_serve_destroy(None) == O.OK
+    assert O.lib().opf_serve_now() > 0
