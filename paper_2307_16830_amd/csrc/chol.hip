@@ -361,63 +361,83 @@ __global__ __launch_bounds__(NT) void blk_potrf(const int32_t* __restrict__ it, 
                 rdiag, status, pr, colbuf, &badmin);
 }
 
-// X <- X L_D^{-T} below the diagonal block: one thread per panel row, 64 rows per work-group, the row in
-// registers.  L_D and its reciprocal pivots come from the compact copy left by the diagonal-block
-// kernel (slot = item field 3); they are read-only here and addressed uniformly with fixed offsets, so
-// they are fetched through the scalar unit into scalar registers and feed the FMAs directly (no LDS).
-// The identity padding of a partial block lets the fully unrolled substitution run without guards;
-// the columns past kb are never stored.
-constexpr int TR = 64;  // panel rows per work-group
-
-__global__ __launch_bounds__(TR) void blk_trsm(const int32_t* __restrict__ it, const int32_t* __restrict__ ncol,
-                                               const int32_t* __restrict__ mrows, const int64_t* __restrict__ foff,
-                                               const double* __restrict__ ldiag, const double* __restrict__ rdiag,
-                                               double* __restrict__ fronts) {
-    const int s = it[4 * blockIdx.x], k0 = it[4 * blockIdx.x + 1], rb = it[4 * blockIdx.x + 2];
-    const int slot = it[4 * blockIdx.x + 3];
-    const int m = mrows[s];
-    const int kb = min(TB, ncol[s] - k0);
-    const int last = kb - 1;
-    const double* Lc = ldiag + (int64_t)slot * TB * TB;
-    const double* rc = rdiag + (int64_t)slot * TB;
-    // The compact block was just written from one compute unit; pull it into this die's L2 with a few
-    // wide vector loads so that the scalar loads below hit there instead of going to memory one by one.
-    {
-        const double2* L2v = reinterpret_cast<const double2*>(Lc);
-#pragma unroll
-        for (int b = 0; b < 4; b++) {
-            double2 v[8];
-#pragma unroll
-            for (int c = 0; c < 8; c++) v[c] = L2v[(b * 8 + c) * TR + threadIdx.x];
-#pragma unroll
-            for (int c = 0; c < 8; c++) asm volatile("" ::"v"(v[c].x), "v"(v[c].y));
-        }
-        const double r = rc[threadIdx.x];
-        asm volatile("" ::"v"(r));
-    }
-    const int row = k0 + kb + rb * TR + threadIdx.x;
-    if (row >= m) return;
-    double* X = fronts + foff[s] + row + (int64_t)m * k0;  // X[m j] = entry (row, k0 + j)
-    // column indices clamped to the last valid column keep the code free of branches (uniform guards
-    // here make the compiler hoist the scalar loads and spill them); the stores run last column
-    // first, so the clamped duplicates are overwritten by the valid value.
-    double x[TB];
-#pragma unroll
-    for (int j = 0; j < TB; j++) x[j] = X[(int64_t)m * min(j, last)];
-#pragma unroll
-    for (int j = 0; j < TB; j++) {
-        x[j] *= rc[j];
-#pragma unroll
-        for (int t = j + 1; t < TB; t++) x[t] -= x[j] * Lc[t + TB * j];
-    }
-#pragma unroll
-    for (int j = TB - 1; j >= 0; j--) X[(int64_t)m * min(j, last)] = x[j];
-}
+constexpr int TR = 64;  // panel rows per work-group of the panel solve
 
 // C(bi, bj) -= P_bi P_bj^T on the trailing matrix, 128 x 128 tiles, FP64 MFMA 16x16x4.
 // Four waves in a 2 x 2 arrangement, each computing a 64 x 64 quadrant as 4 x 4 MFMA blocks;
 // the panel rows are staged through LDS in chunks of 16 columns.
 typedef double double4_t __attribute__((ext_vector_type(4)));
+
+// Panel solve X <- X L_D^{-T} on 64 panel rows per work-group (item: front, k0, row block, slot) with FP64
+// MFMA.  L_D (identity padded) is split into 4 x 4 blocks of 16.  Wave b first inverts the diagonal block L_bb into
+// LDS (lane q computes column q by forward substitution; L_bb and the reciprocal pivots are uniform, so
+// they come through the scalar unit).  Then wave w takes rows [16 w, 16 w + 16) of the work-group's rows
+// through the column blocks in order, Y_b = (X_b - sum_{a<b} Y_a L_ba^T) inv(L_bb)^T, computed transposed
+// (Y_b^T = inv(L_bb) (X_b - ...)^T) so that every product is a 16x16x4 MFMA.  In this layout a lane holds
+// row lane % 16 and columns lane / 16 + 4 r of a 16 x 16 block: that is both the accumulator layout and
+// the B-operand layout, so the solved blocks feed the later updates straight from registers, and the
+// stores put 16 consecutive rows of a column on each 16-lane group.
+__global__ __launch_bounds__(NT) void blk_trsm_mma(const int32_t* __restrict__ it, const int32_t* __restrict__ ncol,
+                                                   const int32_t* __restrict__ mrows,
+                                                   const int64_t* __restrict__ foff, const double* __restrict__ ldiag,
+                                                   const double* __restrict__ rdiag, double* __restrict__ fronts) {
+    __shared__ double inv[4][16][17];  // inv[b][p][q] = inv(L_bb)[p][q]
+    const int s = it[4 * blockIdx.x], k0 = it[4 * blockIdx.x + 1], rb = it[4 * blockIdx.x + 2];
+    const int slot = it[4 * blockIdx.x + 3];
+    const int m = mrows[s];
+    const int kb = min(TB, ncol[s] - k0);
+    const double* Lc = ldiag + (int64_t)slot * TB * TB;  // Lc[t + 64 j] = L_D(t, j)
+    const double* rc = rdiag + (int64_t)slot * TB;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
+    const int li = lane % 16, lk = lane / 16;
+    {
+        const int b = wave, q = li;  // the four 16-lane groups compute the same columns; group 0 stores
+        double y[16];
+#pragma unroll
+        for (int p = 0; p < 16; p++) {
+            double acc = p == q ? 1.0 : 0.0;
+#pragma unroll
+            for (int t = 0; t < p; t++) acc -= Lc[(16 * b + p) + TB * (16 * b + t)] * y[t];
+            y[p] = acc * rc[16 * b + p];
+        }
+        if (lk == 0)
+#pragma unroll
+            for (int p = 0; p < 16; p++) inv[b][p][q] = y[p];
+    }
+    const int row = k0 + kb + rb * TR + 16 * wave + li;
+    const bool rowok = row < m;
+    double* X = fronts + foff[s] + (rowok ? row : 0) + (int64_t)m * k0;  // X[m j] = entry (row, k0 + j)
+    double4_t y[4];
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < 4; b++) {
+        double4_t acc;
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int j = 16 * b + lk + 4 * r;
+            acc[r] = (rowok && j < kb) ? X[(int64_t)m * j] : 0.0;
+        }
+#pragma unroll
+        for (int a = 0; a < b; a++)
+#pragma unroll
+            for (int kk = 0; kk < 4; kk++)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-Lc[(16 * b + li) + TB * (16 * a + 4 * kk + lk)], y[a][kk],
+                                                           acc, 0, 0, 0);
+        double4_t out = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < 4; kk++)
+            out = __builtin_amdgcn_mfma_f64_16x16x4f64(inv[b][li][4 * kk + lk], acc[kk], out, 0, 0, 0);
+        y[b] = out;
+    }
+    if (rowok)
+#pragma unroll
+        for (int b = 0; b < 4; b++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int j = 16 * b + lk + 4 * r;
+                if (j < kb) X[(int64_t)m * j] = y[b][r];
+            }
+}
 constexpr int KC = 16;
 constexpr int KH = 32;  // panel columns staged in LDS at a time
 
@@ -1381,8 +1401,8 @@ void chol_factor_enqueue(chol_sym* C, const double* kval, hipStream_t st, double
             }
             if (S.t1 > S.t0) {
                 tmark(C, st, 3);
-                hipLaunchKernelGGL(blk_trsm, dim3(S.t1 - S.t0), dim3(TR), 0, st, C->trsm_it.p + 4 * S.t0, C->ncol.p,
-                                   C->mrows.p, C->foff.p, C->ldiag.p, C->rdiag.p, C->fronts.p);
+                hipLaunchKernelGGL(blk_trsm_mma, dim3(S.t1 - S.t0), dim3(NT), 0, st, C->trsm_it.p + 4 * S.t0,
+                                   C->ncol.p, C->mrows.p, C->foff.p, C->ldiag.p, C->rdiag.p, C->fronts.p);
                 OPF_LAUNCH_CHECK();
                 tmark(C, st, 3);
             }
