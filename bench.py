@@ -169,7 +169,7 @@ def main():
     ap.add_argument("--serving", type=int, default=32, metavar="REQUESTS",
                     help="also run this many requests of the serving trace through the batched server and one at "
                          "a time (0: skip)")
-    ap.add_argument("--serving-slots", type=int, default=4)
+    ap.add_argument("--serving-slots", type=int, default=8)
     ap.add_argument("--serving-rate", type=float, default=1.5)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of this many MiB (a reference kernel of known "

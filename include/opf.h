@@ -289,7 +289,7 @@ int ipm_direction(ipm_state* state, double* dx, double* ds, double* dy, double* 
  * use from one host thread at a time (its workers are internal threads).
  * ---------------------------------------------------------------------- */
 typedef struct {
-    int32_t slots;        /* worker slots = requests on the device at once (default 4, at most 64) */
+    int32_t slots;        /* worker slots = requests on the device at once (default 8, at most 64) */
     int64_t hbm_budget;   /* bytes of the device pool (default 8 GiB) */
     ipm_options ipm;      /* options of every solve (defaults of ipm_default_options) */
     chol_options chol;    /* analysis options of every solve (defaults of chol_default_options) */

@@ -229,7 +229,7 @@ void worker(opf_server* S, int slot) {
 }  // namespace
 
 extern "C" void serve_default_options(serve_options* o) {
-    o->slots = 4;
+    o->slots = 8;
     o->hbm_budget = int64_t(8) << 30;
     ipm_default_options(&o->ipm);
     chol_default_options(&o->chol);

@@ -438,7 +438,7 @@ def status_name(rc):
             E_NUMERIC: "E_NUMERIC", E_BUDGET: "E_BUDGET"}.get(rc, str(rc))
 
 
-def serve_options(slots=4, hbm_budget=8 << 30, tol=1e-4, max_iter=500, chol_opts=None, **ipm_kw):
+def serve_options(slots=8, hbm_budget=8 << 30, tol=1e-4, max_iter=500, chol_opts=None, **ipm_kw):
     o = ServeOptions()
     lib().serve_default_options(ctypes.byref(o))
     o.slots, o.hbm_budget = int(slots), int(hbm_budget)

@@ -114,7 +114,7 @@ def test_serving_defaults_and_argument_checks():
     O = opf()
     o = O.ServeOptions()
     O.lib().serve_default_options(ctypes.byref(o))
-    assert o.slots == 4 and o.hbm_budget == 8 << 30
+    assert o.slots == 8 and o.hbm_budget == 8 << 30
     assert o.ipm.tol == 1e-4 and o.chol.dense_frac == 0.5
     # argument errors are reported before any device work
     h = ctypes.c_void_p()
