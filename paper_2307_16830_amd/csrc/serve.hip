@@ -18,6 +18,7 @@
 #include <mutex>
 #include <thread>
 #include <unordered_map>
+#include <unordered_set>
 
 #include "common.h"
 
@@ -120,6 +121,7 @@ struct opf_server {
     std::deque<Request> queue;
     std::deque<int64_t> ready;
     std::unordered_map<int64_t, Done> done;
+    std::unordered_set<int64_t> active;  // tags submitted and not finished
     int running = 0;        // admitted, solve not finished
     bool creating = false;  // a slot holds the provisional block
     bool blocked = false;   // the queue head did not fit: admit nothing until memory comes back
@@ -132,6 +134,7 @@ namespace {
 
 void finish(opf_server* S, Done&& d) {
     const int64_t tag = d.r.tag;
+    S->active.erase(tag);
     S->done[tag] = std::move(d);
     S->ready.push_back(tag);
     S->cv_done.notify_all();
@@ -280,10 +283,11 @@ extern "C" int opf_serve_submit(opf_server* S, const opf_grid* grid, int64_t tag
         int rc = opf_create(&rq.grid->g, &rq.model);  // host structure only; device uploads wait for admission
         if (rc != OPF_OK) throw Error{rc};
         std::lock_guard<std::mutex> lk(S->mu);
-        if (S->done.count(tag)) {
+        if (S->done.count(tag) || S->active.count(tag)) {
             opf_destroy(rq.model);
-            OPF_CHECK(false, OPF_E_INVALID, "opf_serve_submit: tag %lld already has a result", (long long)tag);
+            OPF_CHECK(false, OPF_E_INVALID, "opf_serve_submit: tag %lld is already in use", (long long)tag);
         }
+        S->active.insert(tag);
         S->queue.push_back(std::move(rq));
         S->cv_work.notify_one();
     });

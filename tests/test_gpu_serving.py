@@ -106,3 +106,17 @@ def test_request_larger_than_the_pool_is_refused():
     assert r["status"] == opf().E_BUDGET
     assert srv.stats()["in_use"] == 0
     srv.close()
+
+
+def test_reused_tag_is_rejected():
+    (tag, g), = trace_grids(1, 200)
+    srv = opf().Server(slots=1, hbm_budget=1 << 30)
+    srv.submit(g, tag)
+    with pytest.raises(opf().OpfError) as e:
+        srv.submit(g, tag)  # queued or running
+    assert e.value.code == opf().E_INVALID
+    r = drain(srv, 1)[tag]
+    assert r["status"] == 1
+    with pytest.raises(opf().OpfError):
+        srv.submit(g, tag)  # holds a result
+    srv.close()
