@@ -742,25 +742,24 @@ __global__ void fill_sentinel(int64_t n, double* __restrict__ p) {
     if (k < n) p[k] = __longlong_as_double((long long)SENTINEL_BITS);
 }
 
-// Wave 0 waits until block c of zx is complete and leaves it in zs (entries past kc as 0); bounded: after
-// the spin limit the fault word is raised and the block is taken as it is.
-__device__ __forceinline__ void take_block(const double* __restrict__ zx, int c, int kc, double* zs,
-                                           int32_t* __restrict__ fault, bool& alive) {
-    if (threadIdx.x < 64) {
-        double v;
-        int spins = 0;
-        while (true) {
-            v = load_coherent(zx + SB * c + threadIdx.x);
-            if (!alive || !__any(is_sentinel(v))) break;
-            if (++spins > (1 << 20)) {
-                alive = false;
-                if (threadIdx.x == 0) __hip_atomic_store(fault, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
+// The calling wave waits until block c of zx is complete and returns its lane's value of it; every wave
+// polls for itself, so a work-group needs neither LDS nor a barrier per block.  Bounded: past the spin
+// limit the fault word is raised and the block is taken as it is.
+__device__ __forceinline__ double take_block_wave(const double* __restrict__ zx, int c, int32_t* __restrict__ fault,
+                                                  bool& alive) {
+    const int lane = threadIdx.x % 64;
+    double v = load_coherent(zx + SB * c + lane);
+    int spins = 0;
+    while (alive && __any(is_sentinel(v))) {
+        if (++spins > (1 << 20)) {
+            alive = false;
+            if (lane == 0) __hip_atomic_store(fault, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
         }
-        zs[threadIdx.x] = (int)threadIdx.x < kc ? v : 0.0;
+        __builtin_amdgcn_s_sleep(1);
+        v = load_coherent(zx + SB * c + lane);
     }
+    return v;
 }
 
 // forward sweep of one wide front.  Work-group g < nblk owns pivot rows [64g, 64g + 64): it subtracts
@@ -774,7 +773,6 @@ __global__ __launch_bounds__(NT) void wide_fwd(int s, double* __restrict__ zx, i
                                                const int64_t* __restrict__ roff, const int64_t* __restrict__ uoff,
                                                const double* __restrict__ fronts, const double* __restrict__ work,
                                                double* __restrict__ upd, double* __restrict__ y) {
-    __shared__ double zs[SB];
     __shared__ double red[NT / 64][SB];
     const int m = mrows[s], nn = ncol[s], f = first[s];
     const int nblk = (nn + SB - 1) / SB;
@@ -793,6 +791,7 @@ __global__ __launch_bounds__(NT) void wide_fwd(int s, double* __restrict__ zx, i
 #pragma unroll
     for (int j = 0; j < SB; j++) a[j] = (piv && q == 0 && rowok && j < i) ? Lr[(int64_t)m * (r0 + j)] : 0.0;
     if (piv && q == 0 && rowok) rinv = 1.0 / Lr[(int64_t)m * (r0 + i)];
+    const double w0 = (q == 0 && rowok) ? work[roff[s] + r0 + i] : 0.0;  // the right-hand side, also early
     double acc = 0.0;
     bool alive = true;
     for (int c = 0; c < ncb; c++) {
@@ -803,16 +802,14 @@ __global__ __launch_bounds__(NT) void wide_fwd(int s, double* __restrict__ zx, i
             const int j = 16 * q + jj;
             lv[jj] = (rowok && j < kc) ? Lr[(int64_t)m * (c0 + j)] : 0.0;
         }
-        take_block(zx, c, kc, zs, fault, alive);
-        __syncthreads();
+        const double zv = take_block_wave(zx, c, fault, alive);
 #pragma unroll
-        for (int jj = 0; jj < 16; jj++) acc += lv[jj] * zs[16 * q + jj];
-        __syncthreads();
+        for (int jj = 0; jj < 16; jj++) acc += lv[jj] * lane_value(zv, 16 * q + jj);
     }
     red[q][i] = acc;
     __syncthreads();
     if (q != 0) return;
-    double wi = rowok ? work[roff[s] + r0 + i] - ((red[0][i] + red[1][i]) + (red[2][i] + red[3][i])) : 0.0;
+    double wi = rowok ? w0 - ((red[0][i] + red[1][i]) + (red[2][i] + red[3][i])) : 0.0;
     if (!piv) {
         if (rowok) upd[uoff[s] + (r0 - nn) + i] = wi;
         return;
@@ -854,6 +851,7 @@ __global__ __launch_bounds__(NT) void wide_bwd(int s, double* __restrict__ zx, i
 #pragma unroll
     for (int t = 0; t < SB; t++) a[t] = (q == 0 && colok && t > j && t < kb) ? Lc[c0 + t] : 0.0;
     if (q == 0 && colok) rinv = 1.0 / Lc[c0 + j];
+    const double t0 = (q == 0 && colok) ? y[f + c0 + j] : 0.0;  // this block's forward solution, also early
     double acc = 0.0;
     for (int r0 = nn; r0 < m; r0 += SB) {
         const int nr = min(SB, m - r0);
@@ -878,16 +876,14 @@ __global__ __launch_bounds__(NT) void wide_bwd(int s, double* __restrict__ zx, i
             const int r = 16 * q + ii;
             lv[ii] = (colok && r < nr) ? Lc[cr0 + r] : 0.0;
         }
-        __syncthreads();
-        take_block(zx, c, nr, xs, fault, alive);
-        __syncthreads();
+        const double xv = take_block_wave(zx, c, fault, alive);
 #pragma unroll
-        for (int ii = 0; ii < 16; ii++) acc += lv[ii] * xs[16 * q + ii];
+        for (int ii = 0; ii < 16; ii++) acc += lv[ii] * lane_value(xv, 16 * q + ii);
     }
     red[q][j] = acc;
     __syncthreads();
     if (q != 0) return;
-    double tj = colok ? y[f + c0 + j] - ((red[0][j] + red[1][j]) + (red[2][j] + red[3][j])) : 0.0;
+    double tj = colok ? t0 - ((red[0][j] + red[1][j]) + (red[2][j] + red[3][j])) : 0.0;
 #pragma unroll
     for (int t = SB - 1; t >= 0; t--) {
         if (t < kb) {
