@@ -791,6 +791,10 @@ __global__ __launch_bounds__(NT) void wide_fwd(int s, double* __restrict__ zx, i
 #pragma unroll
     for (int j = 0; j < SB; j++) a[j] = (piv && q == 0 && rowok && j < i) ? Lr[(int64_t)m * (r0 + j)] : 0.0;
     if (piv && q == 0 && rowok) rinv = 1.0 / Lr[(int64_t)m * (r0 + i)];
+    // the row scaled by its reciprocal pivot: the substitution below then runs on u_i = w_i / L_ii with one
+    // broadcast and one FMA per step (entries on and above the diagonal are 0, so no select is needed)
+#pragma unroll
+    for (int j = 0; j < SB; j++) a[j] *= rinv;
     const double w0 = (q == 0 && rowok) ? work[roff[s] + r0 + i] : 0.0;  // the right-hand side, also early
     double acc = 0.0;
     bool alive = true;
@@ -814,15 +818,12 @@ __global__ __launch_bounds__(NT) void wide_fwd(int s, double* __restrict__ zx, i
         if (rowok) upd[uoff[s] + (r0 - nn) + i] = wi;
         return;
     }
+    double u = wi * rinv;
 #pragma unroll
-    for (int j = 0; j < SB; j++) {
-        if (j < nr) {
-            const double zj = lane_value(wi * rinv, j);
-            wi = i == j ? zj : (i > j ? wi - a[j] * zj : wi);
-        }
-    }
-    store_coherent(zx + SB * g + i, rowok ? wi : 0.0);
-    if (rowok) y[f + r0 + i] = wi;
+    for (int j = 0; j < SB; j++)
+        if (j < nr) u = fma(-a[j], lane_value(u, j), u);
+    store_coherent(zx + SB * g + i, rowok ? u : 0.0);
+    if (rowok) y[f + r0 + i] = u;
 }
 
 // backward sweep of one wide front.  Work-group g owns pivot block b = nblk - 1 - g (columns
@@ -851,6 +852,9 @@ __global__ __launch_bounds__(NT) void wide_bwd(int s, double* __restrict__ zx, i
 #pragma unroll
     for (int t = 0; t < SB; t++) a[t] = (q == 0 && colok && t > j && t < kb) ? Lc[c0 + t] : 0.0;
     if (q == 0 && colok) rinv = 1.0 / Lc[c0 + j];
+    // the column scaled by its reciprocal pivot (see the forward sweep)
+#pragma unroll
+    for (int t = 0; t < SB; t++) a[t] *= rinv;
     const double t0 = (q == 0 && colok) ? y[f + c0 + j] : 0.0;  // this block's forward solution, also early
     double acc = 0.0;
     for (int r0 = nn; r0 < m; r0 += SB) {
@@ -884,15 +888,12 @@ __global__ __launch_bounds__(NT) void wide_bwd(int s, double* __restrict__ zx, i
     __syncthreads();
     if (q != 0) return;
     double tj = colok ? t0 - ((red[0][j] + red[1][j]) + (red[2][j] + red[3][j])) : 0.0;
+    double u = tj * rinv;
 #pragma unroll
-    for (int t = SB - 1; t >= 0; t--) {
-        if (t < kb) {
-            const double xt = lane_value(tj * rinv, t);
-            tj = j == t ? xt : (j < t ? tj - a[t] * xt : tj);
-        }
-    }
-    store_coherent(zx + SB * b + j, colok ? tj : 0.0);
-    if (colok) y[f + c0 + j] = tj;
+    for (int t = SB - 1; t >= 0; t--)
+        if (t < kb) u = fma(-a[t], lane_value(u, t), u);
+    store_coherent(zx + SB * b + j, colok ? u : 0.0);
+    if (colok) y[f + c0 + j] = u;
 }
 
 }  // namespace
