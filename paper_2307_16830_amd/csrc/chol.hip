@@ -579,6 +579,8 @@ __global__ void permute_out(int n, const int32_t* __restrict__ perm, const doubl
     if (k < n) x[perm[k]] = y[k];
 }
 
+constexpr int WIDE = 256;  // fronts with at least this many pivots use the sync-free solves
+
 // Forward sweep for one front: w = b(own rows) + children's partial results; solve with the diagonal
 // block; keep w on the off-diagonal rows as this front's partial result.  w lives in LDS (dynamic, wcap
 // doubles) when the front fits, else in the front's slice of `work`.  The gathers are unrolled by four so
@@ -615,17 +617,21 @@ __global__ __launch_bounds__(NT) void solve_fwd(const int32_t* __restrict__ list
         for (; t < nu; t += NT) w[rl[t]] += uc[t];
         __syncthreads();
     }
+    // reciprocal pivots first (in parallel), then one multiply and one barrier per pivot column; the solved
+    // values go to zz so that no thread rewrites w[j] while others still read it
+    __shared__ double rdg[WIDE], zz[WIDE];
     const double* L = fronts + foff[s];
+    for (int j = threadIdx.x; j < nn; j += NT) rdg[j] = 1.0 / L[j + (int64_t)m * j];
+    __syncthreads();
     for (int j = 0; j < nn; j++) {
-        const double z = w[j] / L[j + (int64_t)m * j];
-        __syncthreads();
-        if (threadIdx.x == 0) w[j] = z;
+        const double z = w[j] * rdg[j];
         for (int i = j + 1 + threadIdx.x; i < m; i += NT) w[i] -= L[i + (int64_t)m * j] * z;
+        if (threadIdx.x == 0) zz[j] = z;
         __syncthreads();
     }
     for (int t = threadIdx.x; t < m; t += NT) {
         if (t < nn)
-            y[f + t] = w[t];
+            y[f + t] = zz[t];
         else
             upd[uoff[s] + (t - nn)] = w[t];
     }
@@ -675,15 +681,17 @@ __global__ __launch_bounds__(NT) void solve_bwd(const int32_t* __restrict__ list
             if (ln == 0) w[j] -= acc;
         }
     }
+    // reciprocal pivots in parallel, then one multiply and one barrier per pivot (solved values in xx)
+    __shared__ double rdg[WIDE], xx[WIDE];
+    for (int j = threadIdx.x; j < nn; j += NT) rdg[j] = 1.0 / L[j + (int64_t)m * j];
     __syncthreads();
     for (int j = nn - 1; j >= 0; j--) {
-        const double xj = w[j] / L[j + (int64_t)m * j];
-        __syncthreads();
-        if (threadIdx.x == 0) w[j] = xj;
+        const double xj = w[j] * rdg[j];
         for (int i = threadIdx.x; i < j; i += NT) w[i] -= L[j + (int64_t)m * i] * xj;
+        if (threadIdx.x == 0) xx[j] = xj;
         __syncthreads();
     }
-    for (int j = threadIdx.x; j < nn; j += NT) y[f + j] = w[j];
+    for (int j = threadIdx.x; j < nn; j += NT) y[f + j] = xx[j];
 }
 
 // ---------------------------------------------------------------- sync-free solves for wide fronts
@@ -696,7 +704,6 @@ __global__ __launch_bounds__(NT) void solve_bwd(const int32_t* __restrict__ list
 // and loads, because the work-groups of a launch sit on dies with separate L2 caches.  A wait is
 // bounded: past the spin limit the fault word is raised and the work-group goes on (the result is then
 // invalid and reported).
-constexpr int WIDE = 256;  // fronts with at least this many pivots use the sync-free solves
 constexpr int WLDS = 8192; // rows of a narrow front's forward vector kept in LDS (64 KB)
 constexpr int SB = 64;     // block edge of the sync-free solves
 
