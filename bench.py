@@ -31,29 +31,32 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-PMC_SUMMARY = os.path.join(HERE, "profiles", "blk_syrk_cfg2_pmc.md")
+def pmc_summary_path(config, kernel):
+    return os.path.join(HERE, "profiles", f"{kernel.split()[0]}_{config}_pmc.md")
 
 
-def blocked_kernels_hash():
-    """Hash of the source of the blocked factorization kernels (diagonal block, panel solve, trailing update):
-    the hardware-counter traffic recorded for the trailing update holds only while this is unchanged."""
+def factor_kernels_hash():
+    """Hash of the source of the factorization kernels (diagonal block, panel solve, trailing update, dense-front
+    tile launch): hardware-counter traffic recorded for them holds only while this is unchanged."""
     import hashlib
     src = open(os.path.join(HERE, "paper_2307_16830_amd", "csrc", "chol.hip")).read()
     a = src.index("constexpr int PW = ")
-    b = src.index("\n}\n", src.index("void blk_syrk(")) + 3
+    b = src.index("// ---------------------------------------------------------------- solves")
     return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 
 
-def recorded_traffic():
-    """HBM bytes per trailing-update launch from the committed counter summary (FETCH_SIZE and WRITE_SIZE runs,
-    scaled by a reference copy), or None if the kernels changed since the counters were taken."""
+def recorded_traffic(config, kernel):
+    """HBM bytes per launch of the roofline kernel on this configuration, from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE runs, scaled by a reference copy), or None when no summary exists for the
+    kernel and configuration or the kernels changed since the counters were taken."""
     try:
-        text = open(PMC_SUMMARY).read()
+        text = open(pmc_summary_path(config, kernel)).read()
     except OSError:
         return None
     h = re.search(r"kernel-source-hash: ([0-9a-f]+)", text)
     t = re.search(r"traffic-bytes-per-launch: ([0-9.e+]+)", text)
-    if not h or not t or h.group(1) != blocked_kernels_hash():
+    c = re.search(r"config: (\w+)", text)
+    if not h or not t or not c or c.group(1) != config or h.group(1) != factor_kernels_hash():
         return None
     return float(t.group(1))
 
@@ -166,7 +169,8 @@ def main():
     ap.add_argument("--config", default="cfg2")
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serving", type=int, default=32, metavar="REQUESTS",
+    ap.add_argument("--no-graphs", action="store_true", help="plain kernel launches instead of graph replay")
+    ap.add_argument("--serving", type=int, default=512, metavar="REQUESTS",
                     help="also run this many requests of the serving trace through the batched server and one at "
                          "a time (0: skip)")
     ap.add_argument("--serving-slots", type=int, default=8)
@@ -197,13 +201,16 @@ def main():
     grid = gridgen.make_config(args.config)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    stream = torch.cuda.current_stream()
-    M = opf.Model(grid)
+    # the IPM runs on a stream of its own (default priority), so that its factorization and solve launch
+    # sequences are captured into HIP graphs and replayed (ipm_options.graphs)
+    stream = torch.cuda.Stream()
+    M = opf.Model(grid, stream=stream.cuda_stream)
     t0 = time.perf_counter()
     # at 80k buses exact minimum degree stops once the minimum degree reaches 1,500 (the rest, ~42.6k columns,
     # is ordered by index into one dense front); below that the relative dense-tail rule alone applies
     copts = opf.chol_options(dense_abs=1500) if args.config == "cfg3" else None
-    ipm = opf.IPM(M, tol=args.tol, max_iter=10000, chol_opts=copts)
+    ipm = opf.IPM(M, tol=args.tol, max_iter=10000, chol_opts=copts, stream=stream.cuda_stream,
+                  graphs=0 if args.no_graphs else 1)
     torch.cuda.synchronize()
     t_analyze = time.perf_counter() - t0
     C = ipm.chol()
@@ -220,15 +227,26 @@ def main():
 
     run(args.warmup)
     torch.cuda.synchronize()
-    # HIP events around each launch of the dominant kernel (the trailing MFMA update) in the timed region
-    C.timing(["trailing_update"])
+    # timed region: exactly K IPM iterations, no per-launch instrumentation (graph replay stays on)
+    C.timing(False)
     t0 = time.perf_counter()
     run(args.steps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    kt = C.timing_read()
     timed = infos[args.warmup:args.warmup + args.steps]
-    # diagnostic (outside the timed region): every factorization kernel category over two more iterations
+    kt_dense = {"launches": 0, "ms": 0.0, "flops": 0.0}
+    if copts is not None and getattr(copts, "tile_min", 0) > 0:
+        C.timing(["dense_front"])
+        run(args.steps)
+        torch.cuda.synchronize()
+        kt_dense = C.timing_read()["dense_front"]
+    # kernel-timing pass right after the timed region (same grid and factorization schedule, the next K
+    # iterations, plain launches): events around every launch of the blocked path's trailing update
+    C.timing(["trailing_update"])
+    run(args.steps)
+    torch.cuda.synchronize()
+    kt_tu = C.timing_read()["trailing_update"]
+    # diagnostic: every factorization kernel category over two more iterations
     C.timing(True)
     run(2)
     torch.cuda.synchronize()
@@ -237,20 +255,31 @@ def main():
     ms = 1e3 * elapsed / args.steps
     fac_ms = np.mean([i["t_factor"] / max(i["factorizations"], 1) for i in timed])
     stage = {k: float(np.mean([i[k] for i in timed])) for k in ("t_ad", "t_assembly", "t_factor", "t_solve")}
+    stage["t_rest"] = ms - sum(stage.values())
     log(f"[bench] {args.steps} iterations in {elapsed:.3f}s = {ms:.2f} ms/iter; stages (ms) {stage}; "
         f"refinement steps/iter {np.mean([i['ir_steps'] for i in timed]):.2f}, "
         f"factorizations/iter {np.mean([i['factorizations'] for i in timed]):.2f}")
     factor_tflops = C.flops / (fac_ms * 1e-3) / 1e12
-    tu = kt["trailing_update"]
-    avg_ms = tu["ms"] / max(tu["launches"], 1)
-    flops_per_launch = tu["flops"] / max(tu["launches"], 1)
-    bytes_per_launch = tu["bytes"] / max(tu["launches"], 1)
-    # the rank-64 update does ~7 flop per algorithmic byte, below the machine balance (78.6 TFLOP/s over
-    # 8 TB/s = 9.8), so HBM bounds it; the MFMA rate is reported beside it
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    if kt_dense["launches"] > 0:
+        kname = "dense_front (dependency-driven tile factorization of the dense fronts, FP64 MFMA)"
+        kt, where = kt_dense, "HIP events around each launch in a pass of K iterations right after the timed region"
+    else:
+        kname = "blk_syrk (FP64 MFMA trailing update of the supernodal fronts)"
+        kt, where = kt_tu, "HIP events around each launch in a pass of K iterations right after the timed region"
+    avg_ms = kt["ms"] / max(kt["launches"], 1)
+    flops_per_launch = kt["flops"] / max(kt["launches"], 1)
+    # the supernodal Schur-complement update is a dense contraction: its bound is the FP64 MFMA rate and its
+    # algorithmic work the factorization flops of the fronts the launch covers
     achieved_tflops = flops_per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
+    tu_avg = kt_tu["ms"] / max(kt_tu["launches"], 1)
     log(f"[bench] factorization kernels per iteration (diagnostic pass): " +
         ", ".join(f"{k} {v['ms'] / 2:.2f} ms/{v['launches'] // 2} launches" for k, v in kt_all.items()))
+    # algorithmic HBM bytes of the AD and assembly stages per iteration, values only (each evaluation's inputs
+    # and outputs; template parameters and index maps excluded): Hessian (x, y in; H out), the new point (x in;
+    # c, J, gradient out) and every line-search trial (x in; c out)
+    trials = float(np.mean([i["ls_trials"] for i in timed]))
+    ad_bytes = 8.0 * (M.n + M.m + M.nnzh) + 8.0 * (M.n + M.m + M.nnzj + M.n) + trials * 8.0 * (M.n + M.m)
+    asm_bytes = 8.0 * (M.nnzh + M.nnzj + M.m + M.n + M.nnzk)
     out = {
         "metric": "ACOPF IPM iter/s at 10k buses",
         "value": args.steps / elapsed,
@@ -268,18 +297,18 @@ def main():
                                f"n={M.n}, m={M.m}, tol={args.tol}",
                    "global_batch": 1, "parallelism": "single GPU"},
         "stages_ms": stage,
-        # algorithmic HBM rates of the two memory-bound stages (values only; index maps and template
-        # parameters excluded): the Hessian evaluation reads x, y and writes H; the condensed assembly
-        # reads H, J, D, Sigma_x and writes K
-        "stage_gbs": {"ad_hessian": 8.0 * (M.n + M.m + M.nnzh) / (stage["t_ad"] * 1e-3) / 1e9,
-                      "assembly": 8.0 * (M.nnzh + M.nnzj + M.m + M.n + M.nnzk) / (stage["t_assembly"] * 1e-3) / 1e9},
+        "stage_gbs": {"ad": ad_bytes / (stage["t_ad"] * 1e-3) / 1e9 if stage["t_ad"] > 0 else None,
+                      "assembly": asm_bytes / (stage["t_assembly"] * 1e-3) / 1e9 if stage["t_assembly"] > 0 else None,
+                      "note": "algorithmic bytes (values only) over stage time from HIP events per iteration; "
+                              "AD = Hessian + constraint/Jacobian/gradient evaluations of the iteration"},
         "analysis_s": t_analyze,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": recorded_traffic(),
-                     "kernel": "blk_syrk (FP64 MFMA trailing update of the supernodal fronts)",
-                     "avg_launch_ms": avg_ms, "bytes_per_launch": bytes_per_launch,
-                     "flops_per_launch": flops_per_launch, "launches": tu["launches"],
-                     "mfma_tflops": achieved_tflops, "mfma_frac": achieved_tflops / PEAK_FP64_TFLOPS},
+        "roofline": {"bound": "mfma", "achieved": achieved_tflops, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved_tflops / PEAK_FP64_TFLOPS, "traffic": recorded_traffic(args.config, kname),
+                     "kernel": kname, "avg_launch_ms": avg_ms, "launches": kt["launches"],
+                     "flops_per_launch": flops_per_launch, "timing": where,
+                     "trailing_update": {"launches": kt_tu["launches"], "avg_launch_ms": tu_avg,
+                                         "tflops": (kt_tu["flops"] / max(kt_tu["launches"], 1)) / (tu_avg * 1e-3)
+                                         / 1e12 if tu_avg > 0 else None}},
         "factorization_tflops": factor_tflops,
         "factor_kernels_ms_per_iter": {k: v["ms"] / 2 for k, v in kt_all.items()},
     }

@@ -72,11 +72,23 @@ typedef struct {
 
 typedef struct opf_model opf_model;
 
+/* Options of a model.  assembly selects how the condensed matrix and the
+ * sparse products J x, J^T v, W x are gathered: 0 (default) term lists sorted
+ * by output and reduced by segmented wave scans, whenever the packed term
+ * codes fit (nnz_jac < 2^22, n < 2^22, m < 2^20 - 2), else per-entry lists;
+ * 1 always per-entry lists (one work-item per output walking its own list). */
+typedef struct {
+    int32_t assembly;
+} opf_options;
+
+void opf_default_options(opf_options* o);
+
 /* Build the model templates, the fixed Jacobian/Hessian COO structure, the
- * condensed-matrix pattern and the assembly maps, and upload them to HBM.
- * Validates sizes and bus indices (OPF_E_INVALID).  The grid arrays are
- * copied; the caller may free them after the call. */
-int opf_create(const opf_grid* grid, opf_model** out);
+ * condensed-matrix pattern and the assembly maps (host), and record their
+ * upload to HBM, which runs on `stream` at the model's first device use.
+ * opts NULL = defaults.  Validates sizes and bus indices (OPF_E_INVALID).
+ * The grid arrays are copied; the caller may free them after the call. */
+int opf_create(const opf_grid* grid, const opf_options* opts, void* stream, opf_model** out);
 int opf_destroy(opf_model* model);
 
 /* Sizes: variables, constraints, Jacobian nonzeros, Hessian (lower, with
@@ -145,6 +157,15 @@ typedef struct {
     /* numeric: a pivot is accepted when it exceeds pivot_tol * |K_jj| (the
      * assembled diagonal entry); default 0, i.e. when it is positive */
     double pivot_tol;
+    /* fronts with at least tile_min pivots are factored by one
+     * dependency-driven tile launch instead of blocked steps; 0 (default)
+     * disables it: experimental, its first device run did not complete */
+    int32_t tile_min;
+    /* a level whose only blocked front has at least pair_min pivots pairs
+     * its 64-column panels: the first panel of a pair updates only the
+     * second one's columns, the second applies both to the rest of the front
+     * as one rank-128 update; 0 (default): never */
+    int32_t pair_min;
 } chol_options;
 
 typedef struct chol_sym chol_sym;
@@ -181,15 +202,17 @@ int chol_factor(chol_sym* sym, const double* kval, void* stream, int32_t* bad_co
 int chol_solve(chol_sym* sym, const double* b, double* x, int32_t nrhs, void* stream);
 /* Kernel timing of the numeric factorizations (measurement aid).  `mask`
  * selects categories by bit: 1 assembly, 2 small fronts, 4 diagonal-block
- * Cholesky, 8 panel solve, 16 trailing MFMA update (0 disables).  Every
- * launch of a selected category is bracketed by HIP events on the stream it
- * runs on (the events themselves add a little latency between launches);
- * chol_timing_read returns, per category, the summed kernel milliseconds
- * ms[5], the launch counts launches[5], and the algorithmic flops flops[5]
- * and HBM bytes bytes[5] (filled for the trailing update: the symmetric
- * rank-64 update of each step's lower triangle; bytes = every updated entry
- * read and written once plus the panel rows read once per launch).  Any
- * output pointer may be null.  Calling chol_timing resets them. */
+ * Cholesky, 8 panel solve, 16 trailing MFMA update, 32 dense-front tile
+ * launch (0 disables).  Every launch of a selected category is bracketed by
+ * HIP events on the stream it runs on (the events themselves add a little
+ * latency between launches); chol_timing_read returns, per category, the
+ * summed kernel milliseconds ms[6], the launch counts launches[6], and the
+ * algorithmic flops flops[6] and HBM bytes bytes[6] (flops filled for the
+ * trailing update, the symmetric rank-64 update of each blocked step's lower
+ * triangle, and for the dense-front launch, the factorization flops of its
+ * fronts; bytes for the trailing update: every updated entry read and
+ * written once plus the panel rows read once per launch).  Any output
+ * pointer may be null.  Calling chol_timing resets them. */
 int chol_timing(chol_sym* sym, int mask);
 int chol_timing_read(const chol_sym* sym, double* ms, int64_t* launches, double* flops, double* bytes);
 /* Copy L to the host as CSC in pivot order over the supernodal pattern
@@ -215,6 +238,15 @@ typedef struct {
     double mu_init;    /* default 0.1 */
     double bound_relax;/* default 1e-8 */
     double pivot_tol;  /* pivot acceptance of the factorizations, default 1e-12 (see chol_options) */
+    /* 1 (default): when the state's stream is not the null stream, the
+     * factorization's and the triangular solves' launch sequences are
+     * captured once into HIP graphs and replayed (one graph launch instead of
+     * one launch per kernel; same kernels, same results); 0: plain launches */
+    int32_t graphs;
+    /* 1: second-order correction of a rejected first trial step in the
+     * filter line search (up to 4 corrections, each cutting the
+     * infeasibility by 0.99, Waechter & Biegler 2006); 0 (default): off */
+    int32_t soc;
 } ipm_options;
 
 typedef struct {
@@ -230,6 +262,7 @@ typedef struct {
     int32_t ls_trials, ir_steps, factorizations;
     /* stage times of this iteration in milliseconds (device events) */
     double t_ad, t_assembly, t_factor, t_solve, t_total;
+    int32_t soc_steps;  /* second-order corrections tried in the line search */
 } ipm_iter_info;
 
 typedef struct ipm_state ipm_state;
@@ -243,9 +276,26 @@ int ipm_destroy(ipm_state* state);
 /* One iteration of Algorithm 1.  Returns OPF_OK while iterating, 1 when the
  * convergence test holds (no step taken), or a negative status. */
 int ipm_step(ipm_state* state, ipm_iter_info* info);
-/* Iterate until converged or failed; *iters and *obj receive the iteration
- * count and final unscaled objective. */
-int ipm_solve(ipm_state* state, int32_t* iters, double* obj);
+
+typedef struct {
+    int32_t status;      /* 1 converged, else the negative opf_status that ended the solve */
+    int32_t iterations;  /* iterations taken (steps of Algorithm 1) */
+    double objective;    /* unscaled objective at the final iterate */
+    double e0;           /* scaled optimality error (mu = 0) at the final iterate */
+    double inf_pr, inf_du;  /* its scaled primal and dual infeasibility */
+    int32_t factorizations, ir_steps;  /* totals over the solve */
+    /* stage times summed over the solve, milliseconds (device events; t_total host clock) */
+    double t_ad, t_assembly, t_factor, t_solve, t_total;
+    /* device pointers to the final primal iterate x [n], slacks s [m] and
+     * multipliers y [m]; owned by the state, valid until it is destroyed or
+     * stepped again */
+    const double *x, *s, *y;
+} ipm_result;
+
+/* Iterate until converged or failed and fill *out (may be NULL).  Returns
+ * OPF_OK when converged, else the status that ended the solve (also in
+ * out->status). */
+int ipm_solve(ipm_state* state, ipm_result* out);
 /* Host copies of the current primal iterate x [n], slacks s [m] and multipliers y [m]. */
 int ipm_get_iterate(const ipm_state* state, double* x, double* s, double* y);
 /* The analysis used by the IPM (owned by the state). */

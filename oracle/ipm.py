@@ -66,6 +66,10 @@ class Options:
     # a pivot counts as positive only above pivot_tol * |K_jj|: at that size its sign is within
     # rounding noise of the condensed matrix, so regularization is applied instead
     pivot_tol: float = 1e-12
+    # second-order correction of a rejected first trial step (filter line search extension); off by default
+    soc: bool = False
+    soc_max: int = 4               # p_max: corrections per iteration
+    kappa_soc: float = 0.99        # a correction must reduce the infeasibility by this factor to continue
 
 
 class Status:
@@ -293,8 +297,13 @@ class IPM:
         dw, trials = out
         if dw is None:
             return None, None, trials, 0
+        d, nir = self.refined_solve([-v for v in F], hr, hc, hv, Jm, dw)
+        return d, dw, trials, nir
+
+    def refined_solve(self, R0, hr, hc, hv, Jm, dw):
+        """J_F d = R0 through the current factor, with iterative refinement on the full system."""
+        Sx, Ss, dist = self.sigmas()
         Wm = okkt.sym_from_lower(self.n, hr, hc, hv)
-        R0 = [-v for v in F]
         d = self.reduce_solve(R0, Jm, Sx, Ss, dist, dw)
         nr0 = max(np.max(np.abs(v)) for v in R0)
         nir = 0
@@ -308,7 +317,7 @@ class IPM:
             corr = self.reduce_solve(res, Jm, Sx, Ss, dist, dw)
             d = [a + b for a, b in zip(d, corr)]
             nir += 1
-        return d, dw, trials, nir
+        return d, nir
 
     def step_to_boundary(self, tau, d):
         dx, ds, dy, dzl, dzu, dvl, dvu = d
@@ -341,6 +350,44 @@ class IPM:
 
     def filter_ok(self, th, ph):
         return all(th < tf or ph < pf for tf, pf in self.filter)
+
+    def acceptable(self, tht, pht, alpha, th0, ph0, gphi):
+        """Filter and sufficient-decrease test of a trial point: (accepted, f-type step)."""
+        o = self.o
+        if not (np.isfinite(tht) and np.isfinite(pht) and tht < self.theta_max and self.filter_ok(tht, pht)):
+            return False, False
+        switching = gphi < 0 and alpha * (-gphi) ** o.s_phi > o.delta * th0 ** o.s_theta
+        if th0 <= self.theta_min and switching:
+            return pht <= ph0 + o.eta_phi * alpha * gphi, True
+        return tht <= (1.0 - o.gamma_theta) * th0 or pht <= ph0 - o.gamma_phi * th0, False
+
+    def second_order_correction(self, mu, tau, F, hr, hc, hv, Jm, dw, c, alpha0, ct, st_, th0, ph0, gphi):
+        """Second-order correction after the first trial point (step alpha0) was rejected with a larger
+        infeasibility than the current point (Waechter-Biegler 2006, Section 2.4): the same Newton matrix is
+        solved again with the constraint residual replaced by the accumulated
+        c_soc = alpha0 (c(x) - s) + (c(x_trial) - s_trial), up to soc_max times while each correction cuts the
+        infeasibility by kappa_soc.  Returns (direction, alpha, alpha_z, f-type) of an accepted corrected step,
+        or None."""
+        o = self.o
+        c_soc = alpha0 * (c - self.s) + (ct - st_)
+        th_old = float(np.sum(np.abs(ct - st_)))
+        for p in range(1, o.soc_max + 1):
+            R = [-F[0], -F[1], -c_soc, -F[3], -F[4], -F[5], -F[6]]
+            d, _ = self.refined_solve(R, hr, hc, hv, Jm, dw)
+            a, az = self.step_to_boundary(tau, d)
+            xs = self.x + a * d[0]
+            ss = self.s + a * d[1]
+            cs = self.cons(xs)
+            ths = float(np.sum(np.abs(cs - ss)))
+            phs = self.barrier(xs, ss, mu)
+            ok, ftype = self.acceptable(ths, phs, alpha0, th0, ph0, gphi)
+            if ok:
+                return d, a, az, ftype
+            if p == o.soc_max or ths > o.kappa_soc * th_old:
+                return None
+            c_soc = a * c_soc + (cs - ss)
+            th_old = ths
+        return None
 
     # ------------------------------------------------------------ one iteration
     def step(self):
@@ -405,25 +452,29 @@ class IPM:
                     amin = o.gamma_alpha * min(o.gamma_theta, o.gamma_phi * th0 / (-gphi))
             else:
                 amin = o.gamma_alpha * o.gamma_theta
+            nsoc = 0
             while True:
                 nls += 1
                 xt = self.x + alpha * dx
                 st = self.s + alpha * ds
-                tht = self.theta(xt, st)
+                ct = self.cons(xt)
+                tht = float(np.sum(np.abs(ct - st)))
                 pht = self.barrier(xt, st, mu)
-                ok = False
-                ftype = False
-                if np.isfinite(tht) and np.isfinite(pht) and tht < self.theta_max and self.filter_ok(tht, pht):
-                    switching = gphi < 0 and alpha * (-gphi) ** o.s_phi > o.delta * th0 ** o.s_theta
-                    if th0 <= self.theta_min and switching:
-                        ok = pht <= ph0 + o.eta_phi * alpha * gphi
-                        ftype = True
-                    else:
-                        ok = tht <= (1.0 - o.gamma_theta) * th0 or pht <= ph0 - o.gamma_phi * th0
+                ok, ftype = self.acceptable(tht, pht, alpha, th0, ph0, gphi)
                 if ok:
                     accepted = True
                     augment = not ftype
                     break
+                if o.soc and nls == 1 and tht >= th0:
+                    corr = self.second_order_correction(mu, tau, F, hr, hc, hv, Jm, dw, c, alpha, ct, st, th0, ph0,
+                                                        gphi)
+                    nsoc += 1
+                    if corr is not None:
+                        d, alpha, az, ftype = corr
+                        dx, ds, dy, dzl, dzu, dvl, dvu = d
+                        accepted = True
+                        augment = not ftype
+                        break
                 alpha *= 0.5
                 if alpha < amin:
                     break
@@ -442,7 +493,8 @@ class IPM:
         self.vl = self.vl + az * dvl
         self.vu = self.vu + az * dvu
         self._safeguard(mu)
-        info.update({"dw": dw, "alpha": alpha, "alpha_z": az, "ls": nls, "ir": nir, "trials": trials})
+        info.update({"dw": dw, "alpha": alpha, "alpha_z": az, "ls": nls, "ir": nir, "trials": trials,
+                     "soc": 0 if tiny else nsoc})
         self.log.append(info)
         self.iter += 1
         return None

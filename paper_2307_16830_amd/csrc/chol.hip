@@ -32,6 +32,9 @@
 
 using namespace opf;
 
+constexpr int NCAT = 6;  // timing categories: assembly, small fronts, diagonal block, panel solve, trailing update,
+                         // dense-front tile launch
+
 struct chol_sym {
     Symbolic S;
     chol_options opts{};
@@ -57,6 +60,7 @@ struct chol_sym {
         int32_t p0, p1, t0, t1;
         int32_t s0, s1;  // trailing-update tiles of the next panel's 64 columns
         int32_t r0, r1;  // trailing-update tiles of the columns after it
+        int32_t kw;      // columns of L applied by the trailing update (64, or up to 128 for a panel pair)
     };
     std::vector<Step> steps;
     std::vector<int32_t> lvl_step_ptr;
@@ -90,14 +94,34 @@ struct chol_sym {
     std::vector<hipEvent_t> ev_pool;
     std::vector<int> ev_cat;
     size_t ev_used = 0;
-    double t_ms[5] = {0, 0, 0, 0, 0};
-    int64_t t_launch[5] = {0, 0, 0, 0, 0};
-    double t_flops[5] = {0, 0, 0, 0, 0};
-    double t_bytes[5] = {0, 0, 0, 0, 0};
+    double t_ms[NCAT] = {};
+    int64_t t_launch[NCAT] = {};
+    double t_flops[NCAT] = {};
+    double t_bytes[NCAT] = {};
+    // dense fronts (ncol >= DENSE_MIN): one dependency-driven tile launch per level
+    std::vector<int32_t> lvl_dense_ptr;  // [nlevels + 1] task ranges
+    std::vector<double> lvl_dense_flops;  // factorization flops of the level's dense fronts
+    std::vector<char> is_dense;          // per supernode
+    int dense_grid = 0;
+    int32_t epoch = 0;
+    DBuf<int32_t> dh_s, dh_np, dh_nb, dh_slot0, dtask_h, dtask_rc, dflags, dcounter, ffault;
+    DBuf<int64_t> dh_t0;
+    DBuf<double> tdiag, trdiag;
     std::vector<double> step_syrk_flops;  // algorithmic flops of each blocked step's trailing update
     std::vector<double> step_syrk_bytes;  // and its algorithmic HBM bytes (C read + written, panel read once)
+    // HIP graphs of the factorization and solve launch sequences, replayed instead of re-enqueued (set by the
+    // IPM for its own non-null stream): key = (stream, first pointer, second pointer, pivot tolerance)
+    struct GraphEntry {
+        hipStream_t st;
+        const void *a, *b;
+        double tol;
+        hipGraphExec_t exec;
+    };
+    bool use_graphs = false;
+    std::vector<GraphEntry> graphs;
     ~chol_sym() {
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+        for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
     }
 };
 
@@ -345,7 +369,7 @@ __device__ __forceinline__ void potrf_block(int s, int k0, int slot, const int32
     // lane i of the wave owning column i holds that pivot's reciprocal
     if (lane >= PW * w && lane < PW * w + PW) rdiag[(int64_t)slot * TB + lane] = myrinv;
     __syncthreads();
-    if (threadIdx.x == 0 && *badmin < INT_MAX) status[s] = min(status[s], p0 + *badmin);
+    if (threadIdx.x == 0 && *badmin < INT_MAX) atomicMin(&status[s], p0 + *badmin);
 }
 
 // Diagonal blocks of the first blocked step of each front (later steps factor theirs inside the
@@ -534,7 +558,7 @@ __device__ __forceinline__ void tile_mma(double* __restrict__ F, int m, int ri0,
 // a front's next-panel diagonal tile goes on to factor that panel's diagonal block, which it has just
 // brought up to date, into ldiag slot pslot[item] (-1: no such block), while the other work-groups are
 // still updating the rest: the diagonal-block Cholesky of step k+1 hides under the update of step k.
-__global__ __launch_bounds__(NT, 2) void blk_syrk(const int32_t* __restrict__ it, int nitems, int nnext,
+__global__ __launch_bounds__(NT, 2) void blk_syrk(const int32_t* __restrict__ it, int nitems, int nnext, int kw,
                                                const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
                                                const int64_t* __restrict__ foff, double* __restrict__ fronts,
                                                const int32_t* __restrict__ pslot,
@@ -551,7 +575,7 @@ __global__ __launch_bounds__(NT, 2) void blk_syrk(const int32_t* __restrict__ it
         const int s = it[4 * item], k0 = it[4 * item + 1];
         const int ri0 = it[4 * item + 2], rj0 = it[4 * item + 3];
         const int m = mrows[s];
-        const int kb = min(TB, ncol[s] - k0);
+        const int kb = min(kw, ncol[s] - k0);
         double* F = fronts + foff[s];
         const int nri = min(ST, m - ri0);
         if (item < nnext)
@@ -564,6 +588,263 @@ __global__ __launch_bounds__(NT, 2) void blk_syrk(const int32_t* __restrict__ it
                         &badmin);
         }
     }
+}
+
+// ---------------------------------------------------------------- dense fronts: one dependency-driven launch
+// Fronts with at least DENSE_MIN pivots (the dense root of an expander-like grid holds almost all the
+// factorization's flops) are factored tile by tile in one persistent launch instead of one blocked step at a
+// time.  The front's rows are cut into blocks of DT: the pivot columns [0, nn) first (the last pivot block
+// may be short), then the update rows [nn, m).  Every lower tile (bi, bj) is a task; tasks are numbered
+// column by column (diagonal tile first) and work-groups take them in that order from a counter.  A task
+// gathers its tile once, subtracts L(bi, k) L(bj, k)^T for every pivot block k < bj as soon as both tiles are
+// final (left-looking, so the tile is read and written once), and then
+//   * diagonal tile of a pivot block: factors it (the pipelined diagonal-block Cholesky), leaving L_jj and
+//     its reciprocal pivots in the front's slot of tdiag / trdiag;
+//   * tile below a diagonal tile: waits for that diagonal tile and solves X L_jj^{-T} (16 x 16 diagonal
+//     inverses, block substitution on MFMA, as in the panel solve);
+//   * tile of the update block: is left as the update matrix.
+// A finished pivot-column tile is published by a release fence and its flag set to the factorization's
+// epoch; readers spin (bounded) on the flag and acquire.  Every dependency of a task has a smaller task
+// number, and a task is only ever taken by a running work-group, so the smallest unfinished task always
+// progresses: no deadlock whatever the residency.  A wait that exceeds its bound raises the fault word and
+// proceeds (the factor is then reported invalid).
+constexpr int DT = 64;           // tile edge
+// Fronts with at least chol_options.tile_min pivots take the tile path; 0 (the default) switches it off: its
+// first GPU run did not finish (see the design notes), and it stays off until that is explained.
+constexpr int LDT = DT + 1;      // padded LDS row of a staged tile
+constexpr int FLAG_SPINS = 1 << 24;  // ~1 s of polling
+
+struct DenseDesc {
+    const int32_t* hs;       // supernode of each dense front
+    const int32_t* hnp;      // pivot blocks
+    const int32_t* hnb;      // all blocks
+    const int64_t* htask0;   // first task number of the front
+    const int32_t* hslot0;   // first diagonal slot of the front in tdiag / trdiag
+    const int32_t* task_h;   // per task: dense-front index
+    const int32_t* task_rc;  // per task: (bi << 16) | bj
+    int32_t* flags;          // per task: epoch at which the tile became final
+    int32_t* counter;        // task counter of the launch
+    int32_t* fault;          // raised by a wait past its bound
+    double* tdiag;           // 64 x 64 factored diagonal blocks (column-major, identity padding)
+    double* trdiag;          // their reciprocal pivots
+};
+
+__device__ __forceinline__ int blk_start(int b, int np, int nn) { return b < np ? DT * b : nn + DT * (b - np); }
+__device__ __forceinline__ int blk_size(int b, int np, int nn, int m) {
+    return b < np ? min(DT, nn - DT * b) : min(DT, m - (nn + DT * (b - np)));
+}
+// task number of tile (bi, bj), bi >= bj, of a front with nb blocks (column-major lower enumeration)
+__device__ __forceinline__ int64_t tile_task(int64_t t0, int nb, int bi, int bj) {
+    return t0 + (int64_t)bj * nb - (int64_t)bj * (bj - 1) / 2 + (bi - bj);
+}
+
+// Thread 0 waits until the flag holds `epoch` (bounded), then the work-group acquires at agent scope.
+__device__ __forceinline__ void wait_final(const int32_t* flag, int epoch, int32_t* fault, int* ok_sh) {
+    if (threadIdx.x == 0) {
+        int spins = 0, ok = 1;
+        while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+            ++spins;
+            // past the bound, or once any wait of the launch has given up, stop waiting
+            if (spins > FLAG_SPINS ||
+                ((spins & 255) == 0 && __hip_atomic_load(fault, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+                ok = 0;
+                __hip_atomic_store(fault, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        *ok_sh = ok;
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// Every thread's stores of the tile reach agent scope, then thread 0 sets the flag.
+__device__ __forceinline__ void publish_final(int32_t* flag, int epoch) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(flag, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ __launch_bounds__(NT, 2) void dense_front(int64_t t0, int64_t t1, DenseDesc D, int epoch,
+                                                   const int32_t* __restrict__ first,
+                                                   const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
+                                                   const int64_t* __restrict__ foff, double* __restrict__ fronts,
+                                                   int32_t* __restrict__ status, PivotRef pr) {
+    // two staged tiles (k-major: lds[t][r] = tile entry (r, t)); the first also serves as the diagonal-block
+    // Cholesky's 64 x 64 column buffer and as the right-hand side of the triangular solve
+    __shared__ __attribute__((aligned(16))) double Pa[DT * LDT];
+    __shared__ __attribute__((aligned(16))) double Pb[DT * LDT];
+    __shared__ double inv[4][16][17];
+    __shared__ int task_sh, ok_sh, badmin;
+    static_assert(DT * LDT >= TB * TB, "the column buffer of the diagonal-block Cholesky fits");
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
+    const int li = lane % 16, lk = lane / 16;
+    const int wr = wave % 2, wc = wave / 2;  // quadrant of the tile owned by this wave in the update
+    const int qr = 32 * wr, qc = 32 * wc;
+    while (true) {
+        if (threadIdx.x == 0) task_sh = (int)(t0 + atomicAdd(D.counter, 1));
+        __syncthreads();
+        const int64_t t = task_sh;
+        __syncthreads();  // every thread has read task_sh before thread 0 may overwrite it
+        if (t >= t1) break;
+        const int h = D.task_h[t];
+        const int bi = D.task_rc[t] >> 16, bj = D.task_rc[t] & 0xffff;
+        const int s = D.hs[h], np = D.hnp[h], nb = D.hnb[h];
+        const int m = mrows[s], nn = ncol[s];
+        const int64_t ht0 = D.htask0[h];
+        double* F = fronts + foff[s];
+        const int ri0 = blk_start(bi, np, nn), nri = blk_size(bi, np, nn, m);
+        const int rj0 = blk_start(bj, np, nn), nrj = blk_size(bj, np, nn, m);
+        const bool diag = bi == bj;
+        const bool active = !(diag && wc > wr);  // the strictly upper quadrant of a diagonal tile is idle
+        double4_t acc[2][2];
+#pragma unroll
+        for (int a = 0; a < 2; a++)
+#pragma unroll
+            for (int b = 0; b < 2; b++)
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const int i = qr + 16 * a + li, j = qc + 16 * b + lk + 4 * r;
+                    const bool in = active && i < nri && j < nrj && (!diag || i >= j);
+                    acc[a][b][r] = in ? F[(int64_t)(ri0 + i) + (int64_t)m * (rj0 + j)] : 0.0;
+                }
+        // left-looking: every pivot block before this tile's column
+        const int kmax = min(bj, np);
+        for (int k = 0; k < kmax; k++) {
+            const int kc0 = DT * k, kk = min(DT, nn - kc0);
+            wait_final(D.flags + tile_task(ht0, nb, bi, k), epoch, D.fault, &ok_sh);
+            if (!diag) wait_final(D.flags + tile_task(ht0, nb, bj, k), epoch, D.fault, &ok_sh);
+            for (int e = threadIdx.x; e < DT * DT; e += NT) {
+                const int r = e % DT, c = e / DT;
+                double av = 0.0, bv = 0.0;
+                if (c < kk) {
+                    if (r < nri) av = F[(int64_t)(ri0 + r) + (int64_t)m * (kc0 + c)];
+                    if (!diag && r < nrj) bv = F[(int64_t)(rj0 + r) + (int64_t)m * (kc0 + c)];
+                }
+                Pa[c * LDT + r] = -av;
+                Pb[c * LDT + r] = bv;
+            }
+            __syncthreads();
+            if (active) {
+                const double* Pj = diag ? Pa : Pb;
+                const double sg = diag ? -1.0 : 1.0;  // Pa holds the negated rows
+#pragma unroll 4
+                for (int t4 = 0; t4 < DT; t4 += 4) {
+                    double av[2], bv[2];
+#pragma unroll
+                    for (int a = 0; a < 2; a++) av[a] = Pa[(t4 + lk) * LDT + qr + 16 * a + li];
+#pragma unroll
+                    for (int b = 0; b < 2; b++) bv[b] = sg * Pj[(t4 + lk) * LDT + qc + 16 * b + li];
+#pragma unroll
+                    for (int a = 0; a < 2; a++)
+#pragma unroll
+                        for (int b = 0; b < 2; b++)
+                            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[b], av[a], acc[a][b], 0, 0, 0);
+                }
+            }
+            __syncthreads();  // the staged tiles are consumed before the next stage overwrites them
+        }
+        if (bj >= np) {  // update block: the tile is part of the update matrix
+            if (active)
+#pragma unroll
+                for (int a = 0; a < 2; a++)
+#pragma unroll
+                    for (int b = 0; b < 2; b++)
+#pragma unroll
+                        for (int r = 0; r < 4; r++) {
+                            const int i = qr + 16 * a + li, j = qc + 16 * b + lk + 4 * r;
+                            if (i < nri && j < nrj && (!diag || i >= j))
+                                F[(int64_t)(ri0 + i) + (int64_t)m * (rj0 + j)] = acc[a][b][r];
+                        }
+            continue;
+        }
+        const int slot = D.hslot0[h] + bj;
+        int32_t* myflag = D.flags + t;
+        if (diag) {
+            if (active)
+#pragma unroll
+                for (int a = 0; a < 2; a++)
+#pragma unroll
+                    for (int b = 0; b < 2; b++)
+#pragma unroll
+                        for (int r = 0; r < 4; r++) {
+                            const int i = qr + 16 * a + li, j = qc + 16 * b + lk + 4 * r;
+                            if (i < nri && j < nrj && i >= j) F[(int64_t)(ri0 + i) + (int64_t)m * (rj0 + j)] = acc[a][b][r];
+                        }
+            __syncthreads();  // the tile's stores are visible to the work-group; LDS is free
+            potrf_block(s, rj0, slot, first, ncol, mrows, foff, fronts, D.tdiag, D.trdiag, status, pr, Pa, &badmin);
+            publish_final(myflag, epoch);
+            continue;
+        }
+        // off-diagonal tile of a pivot column: X L_jj^{-T} once L_jj is final
+        if (active)
+#pragma unroll
+            for (int a = 0; a < 2; a++)
+#pragma unroll
+                for (int b = 0; b < 2; b++)
+#pragma unroll
+                    for (int r = 0; r < 4; r++) {
+                        const int i = qr + 16 * a + li, j = qc + 16 * b + lk + 4 * r;
+                        Pb[j * LDT + i] = acc[a][b][r];  // X, k-major like the staged tiles
+                    }
+        wait_final(D.flags + tile_task(ht0, nb, bj, bj), epoch, D.fault, &ok_sh);
+        const double* Lc = D.tdiag + (int64_t)slot * TB * TB;  // Lc[t + 64 j] = L_jj(t, j)
+        const double* rc = D.trdiag + (int64_t)slot * TB;
+        const int kb = nrj;
+        {
+            const int b = wave, q = li;  // wave b inverts the diagonal 16 x 16 block b of L_jj
+            double y[16];
+#pragma unroll
+            for (int p = 0; p < 16; p++) {
+                double a = p == q ? 1.0 : 0.0;
+#pragma unroll
+                for (int t2 = 0; t2 < p; t2++) a -= Lc[(16 * b + p) + TB * (16 * b + t2)] * y[t2];
+                y[p] = a * rc[16 * b + p];
+            }
+            if (lk == 0)
+#pragma unroll
+                for (int p = 0; p < 16; p++) inv[b][p][q] = y[p];
+        }
+        __syncthreads();
+        // wave w solves rows [16 w, 16 w + 16) through the four column blocks
+        const int row = 16 * wave + li;
+        double4_t yb[4];
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+            double4_t x;
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int j = 16 * b + lk + 4 * r;
+                x[r] = j < kb ? Pb[j * LDT + row] : 0.0;
+            }
+#pragma unroll
+            for (int a = 0; a < b; a++)
+#pragma unroll
+                for (int q4 = 0; q4 < 4; q4++)
+                    x = __builtin_amdgcn_mfma_f64_16x16x4f64(-Lc[(16 * b + li) + TB * (16 * a + 4 * q4 + lk)],
+                                                             yb[a][q4], x, 0, 0, 0);
+            double4_t out = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int q4 = 0; q4 < 4; q4++)
+                out = __builtin_amdgcn_mfma_f64_16x16x4f64(inv[b][li][4 * q4 + lk], x[q4], out, 0, 0, 0);
+            yb[b] = out;
+        }
+        if (row < nri)
+#pragma unroll
+            for (int b = 0; b < 4; b++)
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const int j = 16 * b + lk + 4 * r;
+                    if (j < kb) F[(int64_t)(ri0 + row) + (int64_t)m * (rj0 + j)] = yb[b][r];
+                }
+        publish_final(myflag, epoch);
+    }
+}
+
+__global__ void reset_counter(int32_t* c) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0;
 }
 
 // ---------------------------------------------------------------- solves
@@ -1110,23 +1391,84 @@ static void build_numeric_plan(chol_sym* C, const std::vector<int32_t>& colptr, 
             }
         }
     }
-    // blocked-path work lists per level and step for fronts with m > 64
+    // dense fronts: tile task lists per level (see dense_front)
+    C->is_dense.assign(ns, 0);
+    for (int s2 = 0; s2 < ns; s2++) C->is_dense[s2] = C->opts.tile_min > 0 && C->h_ncol[s2] >= C->opts.tile_min;
+    std::vector<int32_t> dhs, dhnp, dhnb, dhslot0, dth, dtrc;
+    std::vector<int64_t> dht0;
+    int dslots = 0;
+    C->lvl_dense_ptr.assign(nl + 1, 0);
+    C->lvl_dense_flops.assign(nl, 0.0);
+    for (int l = 0; l < nl; l++) {
+        for (int q = C->lvl_ptr[l]; q < C->lvl_ptr[l + 1]; q++) {
+            const int s2 = C->lvl_sn[q];
+            if (!C->is_dense[s2]) continue;
+            const int m = C->h_mrows[s2], nn = C->h_ncol[s2];
+            const int np = (nn + DT - 1) / DT, nu = (m - nn + DT - 1) / DT, nb = np + nu;
+            OPF_CHECK(nb < 32768, OPF_E_INVALID, "chol_analyze: dense front of %d rows is too large", m);
+            const int h = (int)dhs.size();
+            dhs.push_back(s2);
+            dhnp.push_back(np);
+            dhnb.push_back(nb);
+            dht0.push_back((int64_t)dth.size());
+            dhslot0.push_back(dslots);
+            dslots += np;
+            for (int bj = 0; bj < nb; bj++)
+                for (int bi = bj; bi < nb; bi++) {
+                    dth.push_back(h);
+                    dtrc.push_back((bi << 16) | bj);
+                }
+            for (int j = 0; j < nn; j++) C->lvl_dense_flops[l] += (double)(m - j) * (double)(m - j);
+        }
+        C->lvl_dense_ptr[l + 1] = (int32_t)dth.size();
+    }
+    OPF_CHECK(dth.size() < (size_t)INT32_MAX, OPF_E_INVALID, "chol_analyze: too many dense-front tiles");
+    if (!dhs.empty()) {
+        C->dev.upload(C->dh_s, dhs);
+        C->dev.upload(C->dh_np, dhnp);
+        C->dev.upload(C->dh_nb, dhnb);
+        C->dev.upload(C->dh_t0, dht0);
+        C->dev.upload(C->dh_slot0, dhslot0);
+        C->dev.upload(C->dtask_h, dth);
+        C->dev.upload(C->dtask_rc, dtrc);
+        C->dev.upload(C->dflags, std::vector<int32_t>(dth.size(), 0));
+        C->dev.upload(C->dcounter, std::vector<int32_t>(1, 0));
+        C->dev.alloc(C->tdiag, (int64_t)dslots * TB * TB);
+        C->dev.alloc(C->trdiag, (int64_t)dslots * TB);
+    }
+    C->dev.upload(C->ffault, std::vector<int32_t>(1, 0));
+    // blocked-path work lists per level and step for the other fronts with m > 64.  A level whose only
+    // blocked front has at least chol_options.pair_min pivots (0: never) pairs its 64-column panels: the first panel of a pair
+    // updates only the second panel's columns, and the second panel's step applies both panels to the rest
+    // of the front as one rank-128 update (half the passes over the trailing matrix).
     std::vector<int32_t> pot, trs, syr, nslot;
     int max_slots = 0;
     C->steps.clear();
     C->lvl_step_ptr.assign(nl + 1, 0);
     for (int l = 0; l < nl; l++) {
-        int maxsteps = 0;
+        int maxsteps = 0, nblocked = 0, only = -1;
         for (int q = C->lvl_ptr[l]; q < C->lvl_ptr[l + 1]; q++) {
             int s = C->lvl_sn[q];
-            if (C->h_mrows[s] > TB) maxsteps = std::max(maxsteps, (C->h_ncol[s] + TB - 1) / TB);
+            if (C->h_mrows[s] > TB && !C->is_dense[s]) {
+                maxsteps = std::max(maxsteps, (C->h_ncol[s] + TB - 1) / TB);
+                nblocked++;
+                only = s;
+            }
         }
+        const bool paired = nblocked == 1 && C->opts.pair_min > 0 && C->h_ncol[only] >= C->opts.pair_min;
         for (int k = 0; k < maxsteps; k++) {
-            chol_sym::Step st{l, (int32_t)pot.size() / 2, 0, (int32_t)trs.size() / 4, 0, 0, 0, 0, 0};
+            // pairing: step kind 1 = first panel of a pair, 2 = second panel (rank-128 trailing update)
+            int kind = 0;
+            if (paired) {
+                const int nn = C->h_ncol[only];
+                if (k % 2 == 0 && (k + 1) * TB < nn) kind = 1;
+                if (k % 2 == 1) kind = 2;
+            }
+            chol_sym::Step st{l, (int32_t)pot.size() / 2, 0, (int32_t)trs.size() / 4, 0, 0, 0, 0, 0, TB};
             for (int q = C->lvl_ptr[l]; q < C->lvl_ptr[l + 1]; q++) {
                 int s = C->lvl_sn[q];
                 int m = C->h_mrows[s], nn = C->h_ncol[s];
-                if (m <= TB) continue;
+                if (m <= TB || C->is_dense[s]) continue;
                 int k0 = k * TB;
                 if (k0 >= nn) continue;
                 int kb = std::min(TB, nn - k0);
@@ -1145,17 +1487,24 @@ static void build_numeric_plan(chol_sym* C, const std::vector<int32_t>& colptr, 
             st.p1 = (int32_t)pot.size() / 2;
             st.t1 = (int32_t)trs.size() / 4;
             max_slots = std::max(max_slots, st.p1 - st.p0);
-            // trailing update: the next panel's 64 columns (128 x 64 tiles), then the rest (128 x 128)
+            // trailing update: the next panel's 64 columns (128 x 64 tiles), then the rest (128 x 128); the
+            // items carry the first column of the panels applied, the step their total width
+            const int kfirst = kind == 2 ? (k - 1) * TB : k * TB;
+            if (kind == 2 && only >= 0) st.kw = std::min(k * TB + TB, C->h_ncol[only]) - kfirst;
             for (int pass = 0; pass < 2; pass++) {
                 if (pass == 0)
                     st.s0 = (int32_t)syr.size() / 4;
                 else
                     st.r0 = (int32_t)syr.size() / 4;
+                if (pass == 1 && kind == 1) {  // the first panel of a pair updates the second panel only
+                    st.r1 = (int32_t)syr.size() / 4;
+                    continue;
+                }
                 for (int q = C->lvl_ptr[l]; q < C->lvl_ptr[l + 1]; q++) {
                     int s = C->lvl_sn[q];
                     int m = C->h_mrows[s], nn = C->h_ncol[s];
                     int k0 = k * TB;
-                    if (m <= TB || k0 >= nn) continue;
+                    if (m <= TB || C->is_dense[s] || k0 >= nn) continue;
                     int base = k0 + std::min(TB, nn - k0);
                     int c0 = pass == 0 ? base : base + TB;
                     int c1 = pass == 0 ? std::min(base + TB, m) : m;
@@ -1163,20 +1512,20 @@ static void build_numeric_plan(chol_sym* C, const std::vector<int32_t>& colptr, 
                     for (int rj0 = c0; rj0 < c1; rj0 += cw)
                         for (int ri0 = rj0; ri0 < m; ri0 += ST) {
                             syr.push_back(s);
-                            syr.push_back(k0);
+                            syr.push_back(kfirst);
                             syr.push_back(ri0);
                             syr.push_back(rj0);
                             // the next panel's diagonal tile factors that panel's diagonal block; its slot is
                             // the front's position among the fronts with a panel at the next step
-                            int ns = -1;
+                            int ns2 = -1;
                             if (pass == 0 && ri0 == base && base < nn) {
-                                ns = 0;
+                                ns2 = 0;
                                 for (int q2 = C->lvl_ptr[l]; q2 < q; q2++) {
                                     int s2 = C->lvl_sn[q2];
-                                    if (C->h_mrows[s2] > TB && (k + 1) * TB < C->h_ncol[s2]) ns++;
+                                    if (C->h_mrows[s2] > TB && !C->is_dense[s2] && (k + 1) * TB < C->h_ncol[s2]) ns2++;
                                 }
                             }
-                            nslot.push_back(ns);
+                            nslot.push_back(ns2);
                         }
                 }
                 if (pass == 0)
@@ -1188,13 +1537,22 @@ static void build_numeric_plan(chol_sym* C, const std::vector<int32_t>& colptr, 
             for (int q = C->lvl_ptr[l]; q < C->lvl_ptr[l + 1]; q++) {
                 int s = C->lvl_sn[q];
                 int m = C->h_mrows[s], nn = C->h_ncol[s];
-                if (m <= TB || k * TB >= nn) continue;
-                double kb = std::min(TB, nn - k * TB), r = m - k * TB - kb;
-                fl += r * (r + 1) * kb;  // symmetric rank-kb update of an r x r lower triangle
-                // every lower entry of the r x r block read and written once (16 B); the panel rows read
-                // once by the next-panel tiles and once by the tiles after them
-                const double rest = std::max(0.0, r - TB);
-                by += 16.0 * r * (r + 1) / 2 + 8.0 * kb * (r + rest);
+                if (m <= TB || C->is_dense[s] || k * TB >= nn) continue;
+                const double base = k * TB + std::min(TB, nn - k * TB), r = m - base;
+                if (kind == 1) {
+                    // rank-64 update of the next panel's columns below the diagonal
+                    const double w = std::min<double>(TB, r);
+                    const double ent = w * r - w * (w - 1) / 2;
+                    fl += 2.0 * TB * ent;
+                    by += 16.0 * ent + 8.0 * TB * (r + w);
+                } else {
+                    const double kw = kind == 2 ? st.kw : std::min(TB, nn - k * TB);
+                    fl += r * (r + 1) * kw;  // symmetric rank-kw update of an r x r lower triangle
+                    // every lower entry of the r x r block read and written once (16 B); the panel rows read
+                    // once by the next-panel tiles and once by the tiles after them
+                    const double rest = std::max(0.0, r - TB);
+                    by += 16.0 * r * (r + 1) / 2 + 8.0 * kw * (r + rest);
+                }
             }
             C->step_syrk_flops.push_back(fl);
             C->step_syrk_bytes.push_back(by);
@@ -1260,6 +1618,8 @@ extern "C" void chol_default_options(chol_options* o) {
     o->zero_abs = 64;
     o->zero_rel = 0.05;
     o->pivot_tol = 0.0;
+    o->tile_min = 0;
+    o->pair_min = 0;
 }
 
 extern "C" int chol_analyze(int32_t n, const int32_t* colptr, const int32_t* rowind, const chol_options* opts,
@@ -1371,9 +1731,70 @@ static void tcollect(chol_sym* C) {
     C->ev_used = 0;
 }
 
+__global__ void reset_words(int32_t* a, int32_t* b) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        if (a) *a = 0;
+        if (b) *b = 0;
+    }
+}
+
+static int dense_grid(chol_sym* C) {
+    if (!C->dense_grid) {
+        int dev = 0, cus = 0;
+        OPF_HIP(hipGetDevice(&dev));
+        OPF_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        C->dense_grid = 2 * std::max(cus, 1);  // two work-groups per compute unit (LDS-limited)
+    }
+    return C->dense_grid;
+}
+
+// Run `enqueue` on st, through a captured graph when graphs are enabled: the first call with a key captures
+// the launch sequence (stream capture, thread-local mode) and instantiates it, later calls replay it with one
+// graph launch.  Every captured node is a kernel (no memset or copy nodes); timing mode and the dependency-
+// driven tile path (whose launch carries a per-factorization epoch) run uncaptured.
+template <class F>
+static void run_graph(chol_sym* C, hipStream_t st, const void* a, const void* b, double tol, F&& enqueue) {
+    const bool tiles = !C->lvl_dense_ptr.empty() && C->lvl_dense_ptr.back() > 0;
+    if (!C->use_graphs || !st || C->timing || tiles) {
+        enqueue();
+        return;
+    }
+    for (auto& g : C->graphs)
+        if (g.st == st && g.a == a && g.b == b && g.tol == tol) {
+            OPF_HIP(hipGraphLaunch(g.exec, st));
+            return;
+        }
+    OPF_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    try {
+        enqueue();
+    } catch (...) {
+        hipGraph_t bad = nullptr;
+        (void)hipStreamEndCapture(st, &bad);
+        if (bad) (void)hipGraphDestroy(bad);
+        throw;
+    }
+    hipGraph_t graph = nullptr;
+    OPF_HIP(hipStreamEndCapture(st, &graph));
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    OPF_HIP(e);
+    if (C->graphs.size() >= 8) {
+        (void)hipGraphExecDestroy(C->graphs.front().exec);
+        C->graphs.erase(C->graphs.begin());
+    }
+    C->graphs.push_back({st, a, b, tol, exec});
+    OPF_HIP(hipGraphLaunch(exec, st));
+}
+
 void chol_factor_enqueue(chol_sym* C, const double* kval, hipStream_t st, double pivot_tol) {
     C->dev.run();
     const PivotRef pr{kval, C->kdiagpos.p, pivot_tol};
+    C->epoch++;
+    hipLaunchKernelGGL(reset_words, dim3(1), dim3(64), 0, st, C->ffault.p, (int32_t*)nullptr);
+    OPF_LAUNCH_CHECK();
+    const DenseDesc DD{C->dh_s.p,   C->dh_np.p,    C->dh_nb.p, C->dh_t0.p,    C->dh_slot0.p, C->dtask_h.p,
+                       C->dtask_rc.p, C->dflags.p, C->dcounter.p, C->ffault.p, C->tdiag.p,    C->trdiag.p};
     for (int l = 0; l < C->nlevels; l++) {
         int t0 = C->asm_ptr[l], t1 = C->asm_ptr[l + 1];
         if (t1 > t0) {
@@ -1391,6 +1812,18 @@ void chol_factor_enqueue(chol_sym* C, const double* kval, hipStream_t st, double
                                C->ncol.p, C->mrows.p, C->foff.p, C->fronts.p, C->status.p, pr);
             OPF_LAUNCH_CHECK();
             tmark(C, st, 1);
+        }
+        const int d0 = C->lvl_dense_ptr[l], d1 = C->lvl_dense_ptr[l + 1];
+        if (d1 > d0) {
+            hipLaunchKernelGGL(reset_words, dim3(1), dim3(64), 0, st, C->dcounter.p, (int32_t*)nullptr);
+            OPF_LAUNCH_CHECK();
+            tmark(C, st, 5);
+            hipLaunchKernelGGL(dense_front, dim3(std::min(d1 - d0, dense_grid(C))), dim3(NT), 0, st, (int64_t)d0,
+                               (int64_t)d1, DD, C->epoch, C->first.p, C->ncol.p, C->mrows.p, C->foff.p, C->fronts.p,
+                               C->status.p, pr);
+            OPF_LAUNCH_CHECK();
+            tmark(C, st, 5);
+            if (C->timing & (1 << 5)) C->t_flops[5] += C->lvl_dense_flops[l];
         }
         const int q0 = C->lvl_step_ptr[l], q1 = C->lvl_step_ptr[l + 1];
         for (int q = q0; q < q1; q++) {
@@ -1413,7 +1846,7 @@ void chol_factor_enqueue(chol_sym* C, const double* kval, hipStream_t st, double
             if (S.r1 > S.s0) {
                 tmark(C, st, 4);
                 hipLaunchKernelGGL(blk_syrk, dim3(S.r1 - S.s0), dim3(NT), 0, st, C->syrk_it.p + 4 * S.s0, S.r1 - S.s0,
-                                   S.s1 - S.s0, C->ncol.p, C->mrows.p, C->foff.p, C->fronts.p, C->next_slot.p + S.s0,
+                                   S.s1 - S.s0, S.kw, C->ncol.p, C->mrows.p, C->foff.p, C->fronts.p, C->next_slot.p + S.s0,
                                    C->first.p, C->ldiag.p, C->rdiag.p, C->status.p, pr);
                 OPF_LAUNCH_CHECK();
                 tmark(C, st, 4);
@@ -1435,13 +1868,18 @@ __global__ void init_status(int ns, const int32_t* __restrict__ mrows, int32_t* 
 int chol_factor_sync(chol_sym* C, const double* kval, hipStream_t st, double pivot_tol) {
     C->dev.run();
     const int ns = C->S.nsuper;
-    hipLaunchKernelGGL(init_status, dim3(ceil_div(ns, 256)), dim3(256), 0, st, ns, C->mrows.p, C->status.p);
-    OPF_LAUNCH_CHECK();
-    chol_factor_enqueue(C, kval, st, pivot_tol);
+    run_graph(C, st, kval, nullptr, pivot_tol, [&] {
+        hipLaunchKernelGGL(init_status, dim3(ceil_div(ns, 256)), dim3(256), 0, st, ns, C->mrows.p, C->status.p);
+        OPF_LAUNCH_CHECK();
+        chol_factor_enqueue(C, kval, st, pivot_tol);
+    });
     std::vector<int32_t> stat(ns);
     OPF_HIP(hipMemcpyAsync(stat.data(), C->status.p, ns * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    int32_t ffault = 0;
+    OPF_HIP(hipMemcpyAsync(&ffault, C->ffault.p, sizeof ffault, hipMemcpyDeviceToHost, st));
     OPF_HIP(hipStreamSynchronize(st));
     tcollect(C);
+    OPF_CHECK(ffault == 0, OPF_E_DEVICE, "chol_factor: a dense-front tile wait exceeded its bound");
     int bad_level = INT_MAX, bad = -1;
     for (int s = 0; s < ns; s++)
         if (stat[s] != INT_MAX) {
@@ -1455,10 +1893,19 @@ int chol_factor_sync(chol_sym* C, const double* kval, hipStream_t st, double piv
     return bad;
 }
 
-void chol_solve_enqueue(chol_sym* C, const double* b, double* x, hipStream_t st) {
-    C->dev.run();
+// Device buffers a solve writes besides its output: the permuted working vector y [n], the per-row
+// partial results work [roff[ns]], the update vectors passed to parents upd [upd_total], the exchange
+// blocks of the wide-front sweeps zx [nflags * SB] and the fault word.
+struct SolveBufs {
+    double *y, *work, *upd, *zx;
+    int32_t* fault;
+};
+
+static SolveBufs handle_bufs(chol_sym* C) { return {C->ybuf.p, C->work.p, C->upd.p, C->zx.p, C->sfault.p}; }
+
+static void solve_enqueue(chol_sym* C, const double* b, double* x, hipStream_t st, const SolveBufs& B) {
     const int n = C->n;
-    double* y = C->ybuf.p;
+    double* y = B.y;
     hipLaunchKernelGGL(permute_in, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, C->perm.p, b, y);
     OPF_LAUNCH_CHECK();
     for (int l = 0; l < C->nlevels; l++) {
@@ -1468,25 +1915,25 @@ void chol_solve_enqueue(chol_sym* C, const double* b, double* x, hipStream_t st)
             hipLaunchKernelGGL(solve_fwd, dim3(q1 - q0), dim3(NT), (size_t)wcap * sizeof(double), st,
                                C->lvl_narrow_d.p + q0, C->first.p, C->ncol.p, C->mrows.p, C->foff.p, C->roff.p,
                                C->uoff.p, C->child_ptr.p, C->child.p, C->rel_off.p, C->rel.p, C->fronts.p,
-                               C->work.p, C->upd.p, y, wcap);
+                               B.work, B.upd, y, wcap);
             OPF_LAUNCH_CHECK();
         }
         int w0 = C->lvl_wide_ptr[l], w1 = C->lvl_wide_ptr[l + 1];
         if (w1 > w0) {
             hipLaunchKernelGGL(sfwd_gather, dim3(w1 - w0), dim3(NT), 0, st, C->lvl_wide_d.p + w0, C->first.p,
                                C->ncol.p, C->mrows.p, C->roff.p, C->uoff.p, C->child_ptr.p, C->child.p, C->rel_off.p,
-                               C->rel.p, C->work.p, C->upd.p, y);
+                               C->rel.p, B.work, B.upd, y);
             OPF_LAUNCH_CHECK();
             for (int q = w0; q < w1; q++) {
                 const int s = C->lvl_wide[q];
                 const int m = C->h_mrows[s], nn = C->h_ncol[s];
                 const int g = (nn + SB - 1) / SB + (m - nn + SB - 1) / SB;
-                double* zx = C->zx.p + C->h_flag_off[s] * SB;
+                double* zx = B.zx + C->h_flag_off[s] * SB;
                 const int64_t nz = (int64_t)((nn + SB - 1) / SB) * SB;
                 hipLaunchKernelGGL(fill_sentinel, dim3(ceil_div(nz, 256)), dim3(256), 0, st, nz, zx);
                 OPF_LAUNCH_CHECK();
-                hipLaunchKernelGGL(wide_fwd, dim3(g), dim3(NT), 0, st, s, zx, C->sfault.p, C->first.p, C->ncol.p,
-                                   C->mrows.p, C->foff.p, C->roff.p, C->uoff.p, C->fronts.p, C->work.p, C->upd.p, y);
+                hipLaunchKernelGGL(wide_fwd, dim3(g), dim3(NT), 0, st, s, zx, B.fault, C->first.p, C->ncol.p,
+                                   C->mrows.p, C->foff.p, C->roff.p, C->uoff.p, C->fronts.p, B.work, B.upd, y);
                 OPF_LAUNCH_CHECK();
             }
         }
@@ -1496,18 +1943,18 @@ void chol_solve_enqueue(chol_sym* C, const double* b, double* x, hipStream_t st)
         for (int q = w0; q < w1; q++) {
             const int s = C->lvl_wide[q];
             const int nn = C->h_ncol[s];
-            double* zx = C->zx.p + C->h_flag_off[s] * SB;
+            double* zx = B.zx + C->h_flag_off[s] * SB;
             const int64_t nz = (int64_t)((nn + SB - 1) / SB) * SB;
             hipLaunchKernelGGL(fill_sentinel, dim3(ceil_div(nz, 256)), dim3(256), 0, st, nz, zx);
             OPF_LAUNCH_CHECK();
-            hipLaunchKernelGGL(wide_bwd, dim3((nn + SB - 1) / SB), dim3(NT), 0, st, s, zx, C->sfault.p, C->first.p,
+            hipLaunchKernelGGL(wide_bwd, dim3((nn + SB - 1) / SB), dim3(NT), 0, st, s, zx, B.fault, C->first.p,
                                C->ncol.p, C->mrows.p, C->foff.p, C->roff.p, C->rows.p, C->fronts.p, y);
             OPF_LAUNCH_CHECK();
         }
         int q0 = C->lvl_narrow_ptr[l], q1 = C->lvl_narrow_ptr[l + 1];
         if (q1 > q0) {
             hipLaunchKernelGGL(solve_bwd, dim3(q1 - q0), dim3(NT), 0, st, C->lvl_narrow_d.p + q0, C->first.p,
-                               C->ncol.p, C->mrows.p, C->foff.p, C->roff.p, C->rows.p, C->fronts.p, C->work.p, y);
+                               C->ncol.p, C->mrows.p, C->foff.p, C->roff.p, C->rows.p, C->fronts.p, B.work, y);
             OPF_LAUNCH_CHECK();
         }
     }
@@ -1515,17 +1962,27 @@ void chol_solve_enqueue(chol_sym* C, const double* b, double* x, hipStream_t st)
     OPF_LAUNCH_CHECK();
 }
 
+void chol_solve_enqueue(chol_sym* C, const double* b, double* x, hipStream_t st) {
+    C->dev.run();
+    run_graph(C, st, b, x, -1.0, [&] { solve_enqueue(C, b, x, st, handle_bufs(C)); });
+}
+
+void chol_use_graphs(chol_sym* C, bool on) { C->use_graphs = on; }
+
 // Raised by a sync-free solve whose wait exceeded its bound (the solve result is invalid).
 // The analysis's device buffers and uploads, normally performed at the first factorization, done now.
 void chol_prepare_device(chol_sym* C) { C->dev.run(); }
 
-int chol_solve_fault(chol_sym* C, hipStream_t st) {
+static int read_fault(const chol_sym* C, const int32_t* fault, hipStream_t st) {
     if (C->h_flag_off.empty()) return 0;
     int32_t v = 0;
-    OPF_HIP(hipMemcpyAsync(&v, C->sfault.p, sizeof v, hipMemcpyDeviceToHost, st));
+    OPF_HIP(hipMemcpyAsync(&v, fault, sizeof v, hipMemcpyDeviceToHost, st));
     OPF_HIP(hipStreamSynchronize(st));
     return v;
 }
+
+int chol_solve_fault(chol_sym* C, hipStream_t st) { return read_fault(C, C->sfault.p, st); }
+
 
 }  // namespace opf
 
@@ -1584,9 +2041,9 @@ extern "C" int chol_export_factor(chol_sym* C, int64_t* lp, int32_t* li, double*
 extern "C" int chol_timing(chol_sym* C, int enable) {
     return guarded([&] {
         OPF_CHECK(C, OPF_E_INVALID, "chol_timing: null handle");
-        C->timing = enable & 31;
+        C->timing = enable & ((1 << NCAT) - 1);
         C->ev_used = 0;
-        for (int q = 0; q < 5; q++) {
+        for (int q = 0; q < NCAT; q++) {
             C->t_ms[q] = 0;
             C->t_launch[q] = 0;
             C->t_flops[q] = 0;
@@ -1598,7 +2055,7 @@ extern "C" int chol_timing(chol_sym* C, int enable) {
 extern "C" int chol_timing_read(const chol_sym* C, double* ms, int64_t* launches, double* flops, double* bytes) {
     return guarded([&] {
         OPF_CHECK(C, OPF_E_INVALID, "chol_timing_read: null handle");
-        for (int q = 0; q < 5; q++) {
+        for (int q = 0; q < NCAT; q++) {
             if (ms) ms[q] = C->t_ms[q];
             if (launches) launches[q] = C->t_launch[q];
             if (flops) flops[q] = C->t_flops[q];

@@ -139,19 +139,20 @@ struct DBuf {
 // so that host-only queries (structure, patterns, symbolic analysis) work
 // without touching the GPU.
 struct Deferred {
-    std::vector<std::function<void()>> jobs;
+    std::vector<std::function<void(hipStream_t)>> jobs;
     bool done = false;
+    hipStream_t stream = nullptr;  // the uploads run on this stream (synchronised before run() returns)
     template <class T>
     void upload(DBuf<T>& d, std::vector<T> h) {
-        jobs.push_back([&d, h = std::move(h)]() { d.upload(h); });
+        jobs.push_back([&d, h = std::move(h)](hipStream_t s) { d.upload(h, s); });
     }
     template <class T>
     void alloc(DBuf<T>& d, size_t n) {
-        jobs.push_back([&d, n]() { d.alloc(n); });
+        jobs.push_back([&d, n](hipStream_t) { d.alloc(n); });
     }
     void run() {
         if (done) return;
-        for (auto& j : jobs) j();
+        for (auto& j : jobs) j(stream);
         jobs.clear();
         done = true;
     }

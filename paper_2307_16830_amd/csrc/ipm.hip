@@ -27,6 +27,7 @@ int chol_factor_sync(chol_sym* C, const double* kval, hipStream_t st, double piv
 void chol_solve_enqueue(chol_sym* C, const double* b, double* x, hipStream_t st);
 int chol_solve_fault(chol_sym* C, hipStream_t st);
 void chol_prepare_device(chol_sym* C);
+void chol_use_graphs(chol_sym* C, bool on);
 }  // namespace opf
 
 using namespace opf;
@@ -45,6 +46,8 @@ struct Consts {
            kw_plus = 8.0;
     double ir_stall = 0.9;
     double bound_push = 1e-2, bound_frac = 1e-2;
+    int soc_max = 4;          // second-order corrections per iteration (p_max)
+    double kappa_soc = 0.99;  // each correction must cut the infeasibility by this factor to continue
 };
 
 // distance to a bound: x - lo (lower) or hi - x (upper); absent bounds are +-inf
@@ -369,6 +372,17 @@ __global__ void k_trial(int n, int m, double alpha, const double* x, const doubl
         st[i - n] = s[i - n] + alpha * ds[i - n];
 }
 
+// second-order correction: c_soc = a * c_soc + (ct - st) (a = 0: start from ct - st), and its negation into ry
+__global__ void k_soc(int m, double a, const double* __restrict__ ct, const double* __restrict__ st,
+                      double* __restrict__ csoc, double* __restrict__ ry) {
+    int r = blockIdx.x * EB + threadIdx.x;
+    if (r < m) {
+        const double v = (a == 0.0 ? 0.0 : a * csoc[r]) + (ct[r] - st[r]);
+        csoc[r] = v;
+        ry[r] = -v;
+    }
+}
+
 // accept the step and apply the bound-multiplier safeguard
 __global__ void k_update(int n, int m, double alpha, double az, double mu, double ksig, double* x, double* s,
                          double* y, double* zl, double* zu, double* vl, double* vu, const double* xl,
@@ -416,9 +430,11 @@ struct ipm_state {
     DBuf<double> R0[7], d[7], cr[7], res[7];
     DBuf<double> qx, qs, v, rhs, tmp_n, tmp_m, wdx, jtdy, jdx;
     DBuf<double> xt, stt, ct, ft;
+    DBuf<double> Rs[7], dsoc[7], csoc;  // second-order correction: right-hand side, direction, c_soc
     DBuf<double> part;
     double* host = nullptr;  // pinned scalar outputs
-    hipEvent_t ev[8]{};
+    hipEvent_t ev[10]{};
+    bool own_host = true, own_events = true;  // false when lent by the caller (the solve server's slots)
 };
 
 namespace {
@@ -483,10 +499,11 @@ double read_scalar(ipm_state* S, const double* dptr) {
     return S->host[0];
 }
 
-void eval_point(ipm_state* S) {
+void eval_point(ipm_state* S, hipEvent_t after_eval) {
     // scaled gradient, constraints and Jacobian at x, plus J^T y
     eval_derivs(S->M, OPF_EVAL_F | OPF_EVAL_C | OPF_EVAL_GRAD | OPF_EVAL_JAC, S->x.p, S->y.p, S->sf, S->sc.p,
                 S->sf, S->f.p, S->c.p, S->g.p, S->jac.p, nullptr, S->st);
+    if (after_eval) OPF_HIP(hipEventRecord(after_eval, S->st));
     jt_times(S->M, S->jac.p, S->y.p, nullptr, S->jty.p, S->st);
 }
 
@@ -551,10 +568,24 @@ extern "C" void ipm_default_options(ipm_options* o) {
     o->mu_init = 0.1;
     o->bound_relax = 1e-8;
     o->pivot_tol = 1e-12;
+    o->graphs = 1;
+    o->soc = 0;
 }
+
+// ipm_create with optional parts supplied by the caller (internal, used by the solve server): an analysis
+// already made for the model's condensed pattern (ownership passes to the state), a pinned buffer of 16
+// doubles and 10 events that stay the caller's.  Lets the server run the host analysis before it takes
+// pool memory and keep pinned allocations and events per slot instead of per request.
+int ipm_create_ex(opf_model* M, const ipm_options* opts, const chol_options* copts, void* stream, chol_sym* prebuilt,
+                  double* host, const hipEvent_t* events, ipm_state** out);
 
 extern "C" int ipm_create(opf_model* M, const ipm_options* opts, const chol_options* copts, void* stream,
                           ipm_state** out) {
+    return ipm_create_ex(M, opts, copts, stream, nullptr, nullptr, nullptr, out);
+}
+
+int ipm_create_ex(opf_model* M, const ipm_options* opts, const chol_options* copts, void* stream, chol_sym* prebuilt,
+                  double* host, const hipEvent_t* events, ipm_state** out) {
     return guarded([&] {
         OPF_CHECK(M && out, OPF_E_INVALID, "ipm_create: null argument");
         *out = nullptr;
@@ -568,8 +599,15 @@ extern "C" int ipm_create(opf_model* M, const ipm_options* opts, const chol_opti
             const int n = M->n, m = M->m;
             S->n = n;
             S->m = m;
-            int rc = chol_analyze(n, M->kcolptr.data(), M->krowind.data(), copts, &S->C);
-            if (rc != OPF_OK) throw Error{rc};
+            if (prebuilt) {
+                S->C = prebuilt;
+                prebuilt = nullptr;
+            } else {
+                int rc = chol_analyze(n, M->kcolptr.data(), M->krowind.data(), copts, &S->C);
+                if (rc != OPF_OK) throw Error{rc};
+            }
+            // graphs need a stream of our own to capture on (capture on the null stream is not allowed)
+            chol_use_graphs(S->C, S->o.graphs != 0 && S->st != nullptr);
             for (DBuf<double>* b : {&S->x, &S->zl, &S->zu, &S->xl, &S->xu, &S->g, &S->jty, &S->Sx, &S->dxl, &S->dxu,
                                     &S->qx, &S->rhs, &S->tmp_n, &S->wdx, &S->jtdy, &S->xt})
                 b->alloc(n);
@@ -583,14 +621,31 @@ extern "C" int ipm_create(opf_model* M, const ipm_options* opts, const chol_opti
                 S->cr[q].alloc(lens[q]);
                 S->res[q].alloc(lens[q]);
             }
+            if (S->o.soc) {
+                for (int q = 0; q < 7; q++) {
+                    S->Rs[q].alloc(lens[q]);
+                    S->dsoc[q].alloc(lens[q]);
+                }
+                S->csoc.alloc(m);
+            }
             S->jac.alloc(M->nnzj);
             S->hess.alloc(M->nnzh);
             S->kval.alloc(M->nnzk);
             S->f.alloc(1);
             S->ft.alloc(1);
             S->part.alloc(RED_BLOCKS * 8 + 8);
-            OPF_HIP(hipHostMalloc((void**)&S->host, 16 * sizeof(double)));
-            for (auto& e : S->ev) OPF_HIP(hipEventCreate(&e));
+            if (host) {
+                S->host = host;
+                S->own_host = false;
+            } else {
+                OPF_HIP(hipHostMalloc((void**)&S->host, 16 * sizeof(double)));
+            }
+            if (events) {
+                for (int q = 0; q < 10; q++) S->ev[q] = events[q];
+                S->own_events = false;
+            } else {
+                for (auto& e : S->ev) OPF_HIP(hipEventCreate(&e));
+            }
             // ---- scaling at the user starting point
             std::vector<double> x0 = M->x0;
             OPF_HIP(hipMemcpyAsync(S->x.p, x0.data(), n * 8, hipMemcpyHostToDevice, S->st));
@@ -660,12 +715,13 @@ extern "C" int ipm_create(opf_model* M, const ipm_options* opts, const chol_opti
             up(S->vl, vl);
             up(S->vu, vu);
             S->mu = S->o.mu_init;
-            eval_point(S);
+            eval_point(S, nullptr);
             double th0 = 0, ph0 = 0;
             merit(S, S->x.p, S->s.p, S->c.p, S->mu, 0.0, &th0, &ph0);
             S->theta_max = 1e4 * std::max(1.0, th0);
             S->theta_min = 1e-4 * std::max(1.0, th0);
         } catch (...) {
+            if (prebuilt) chol_destroy(prebuilt);  // not yet handed to the state
             ipm_destroy(S);
             throw;
         }
@@ -676,9 +732,10 @@ extern "C" int ipm_create(opf_model* M, const ipm_options* opts, const chol_opti
 extern "C" int ipm_destroy(ipm_state* S) {
     if (!S) return OPF_OK;
     if (S->C) chol_destroy(S->C);
-    if (S->host) (void)hipHostFree(S->host);
-    for (auto& e : S->ev)
-        if (e) (void)hipEventDestroy(e);
+    if (S->host && S->own_host) (void)hipHostFree(S->host);
+    if (S->own_events)
+        for (auto& e : S->ev)
+            if (e) (void)hipEventDestroy(e);
     delete S;
     return OPF_OK;
 }
@@ -693,6 +750,42 @@ int ipm_prepare_device(ipm_state* S) {
         chol_prepare_device(S->C);
         OPF_HIP(hipStreamSynchronize(S->st));
     });
+}
+
+// X = J_F^{-1} R through the current factor (condensed solve + recovery) with iterative refinement on the
+// full, unreduced system including the regularization dw; returns the refinement steps taken.
+static int refined_solve(ipm_state* S, DBuf<double>* R, DBuf<double>* X, double dw) {
+    const int n = S->n, m = S->m;
+    hipStream_t st = S->st;
+    Vec V = vecs(S);
+    reduce_solve(S, R, X);
+    double nr0, dummy;
+    maxabs7(S, R, nullptr, &nr0, &dummy);
+    double prev = INFINITY;
+    int nir = 0;
+    for (int it = 0; it < S->o.max_ir; it++) {
+        w_times(S->M, S->hess.p, X[0].p, S->wdx.p, st);
+        jt_times(S->M, S->jac.p, X[2].p, nullptr, S->jtdy.p, st);
+        j_times(S->M, S->jac.p, X[0].p, S->jdx.p, st);
+        hipLaunchKernelGGL(k_full_residual, dim3(grid_nm(S)), dim3(EB), 0, st, n, m, V, dw, R[0].p, R[1].p, R[2].p,
+                           R[3].p, R[4].p, R[5].p, R[6].p, X[0].p, X[1].p, X[2].p, X[3].p, X[4].p, X[5].p, X[6].p,
+                           S->wdx.p, S->jtdy.p, S->jdx.p, S->dxl.p, S->dxu.p, S->dsl.p, S->dsu.p, S->res[0].p,
+                           S->res[1].p, S->res[2].p, S->res[3].p, S->res[4].p, S->res[5].p, S->res[6].p);
+        OPF_LAUNCH_CHECK();
+        double rn;
+        maxabs7(S, S->res, nullptr, &rn, &dummy);
+        if (rn <= S->o.ir_tol * std::max(1.0, nr0) || rn > S->K.ir_stall * prev) break;
+        prev = rn;
+        reduce_solve(S, S->res, S->cr);
+        const int lens[7] = {n, m, m, n, n, m, m};
+        for (int q = 0; q < 7; q++) {
+            hipLaunchKernelGGL(k_axpy, dim3(ceil_div(lens[q], EB)), dim3(EB), 0, st, (int64_t)lens[q], 1.0,
+                               S->cr[q].p, X[q].p);
+            OPF_LAUNCH_CHECK();
+        }
+        nir++;
+    }
+    return nir;
 }
 
 // Newton direction at the current iterate for barrier parameter mu: Hessian,
@@ -751,34 +844,7 @@ static int compute_direction(ipm_state* S, double mu, ipm_iter_info& I) {
     I.delta_w = dw;
     // ---- direction + iterative refinement on the full system
     OPF_HIP(hipEventRecord(S->ev[5], st));
-    reduce_solve(S, S->R0, S->d);
-    double nr0, dummy;
-    maxabs7(S, S->R0, nullptr, &nr0, &dummy);
-    double prev = INFINITY;
-    int nir = 0;
-    for (int it = 0; it < S->o.max_ir; it++) {
-        w_times(S->M, S->hess.p, S->d[0].p, S->wdx.p, st);
-        jt_times(S->M, S->jac.p, S->d[2].p, nullptr, S->jtdy.p, st);
-        j_times(S->M, S->jac.p, S->d[0].p, S->jdx.p, st);
-        hipLaunchKernelGGL(k_full_residual, dim3(grid_nm(S)), dim3(EB), 0, st, n, m, V, dw, S->R0[0].p, S->R0[1].p,
-                           S->R0[2].p, S->R0[3].p, S->R0[4].p, S->R0[5].p, S->R0[6].p, S->d[0].p, S->d[1].p,
-                           S->d[2].p, S->d[3].p, S->d[4].p, S->d[5].p, S->d[6].p, S->wdx.p, S->jtdy.p, S->jdx.p,
-                           S->dxl.p, S->dxu.p, S->dsl.p, S->dsu.p, S->res[0].p, S->res[1].p, S->res[2].p,
-                           S->res[3].p, S->res[4].p, S->res[5].p, S->res[6].p);
-        OPF_LAUNCH_CHECK();
-        double rn;
-        maxabs7(S, S->res, nullptr, &rn, &dummy);
-        if (rn <= S->o.ir_tol * std::max(1.0, nr0) || rn > K.ir_stall * prev) break;
-        prev = rn;
-        reduce_solve(S, S->res, S->cr);
-        const int lens[7] = {n, m, m, n, n, m, m};
-        for (int q = 0; q < 7; q++) {
-            hipLaunchKernelGGL(k_axpy, dim3(ceil_div(lens[q], EB)), dim3(EB), 0, st, (int64_t)lens[q], 1.0,
-                               S->cr[q].p, S->d[q].p);
-            OPF_LAUNCH_CHECK();
-        }
-        nir++;
-    }
+    const int nir = refined_solve(S, S->R0, S->d, dw);
     OPF_HIP(hipEventRecord(S->ev[6], st));
     if (chol_solve_fault(S->C, st)) {
         set_error("ipm_step: a triangular-solve block wait exceeded its bound");
@@ -847,7 +913,8 @@ static int ipm_step_impl(ipm_state* S, ipm_iter_info* info) {
     OPF_LAUNCH_CHECK();
     double al[2];
     finish<2>(S, {MIN, MIN}, al);
-    const double amax = al[0], az = al[1];
+    const double amax = al[0];
+    double az = al[1];
     // ---- filter line search
     double th0, ph0;
     merit(S, S->x.p, S->s.p, S->c.p, mu, fs, &th0, &ph0);
@@ -861,6 +928,8 @@ static int ipm_step_impl(ipm_state* S, ipm_iter_info* info) {
     double alpha = amax;
     bool accepted = false, augment = false;
     int nls = 0;
+    double t_trial = 0;  // derivative evaluations of the line-search trial points (ms)
+    int nsoc = 0;        // second-order corrections tried
     if (tiny) {
         accepted = true;
     } else {
@@ -874,44 +943,95 @@ static int ipm_step_impl(ipm_state* S, ipm_iter_info* info) {
         } else {
             amin = K.gamma_alpha * K.gamma_theta;
         }
-        while (true) {
-            nls++;
-            hipLaunchKernelGGL(k_trial, dim3(grid_nm(S)), dim3(EB), 0, st, n, m, alpha, S->x.p, S->d[0].p, S->s.p,
-                               S->d[1].p, S->xt.p, S->stt.p);
+        // filter and sufficient-decrease test of a trial point: (accepted, f-type step)
+        auto acceptable = [&](double tht, double pht, bool inside, double a, bool* ftype) {
+            *ftype = false;
+            if (!(inside && std::isfinite(tht) && std::isfinite(pht) && tht < S->theta_max)) return false;
+            for (auto& p : S->filter)
+                if (!(tht < p.first || pht < p.second)) return false;
+            bool switching = gphi < 0 && a * std::pow(-gphi, K.s_phi) > K.delta * std::pow(th0, K.s_theta);
+            if (th0 <= S->theta_min && switching) {
+                *ftype = true;
+                return pht <= ph0 + K.eta_phi * a * gphi;
+            }
+            return tht <= (1.0 - K.gamma_theta) * th0 || pht <= ph0 - K.gamma_phi * th0;
+        };
+        // trial point x + a dx, s + a ds: constraint values into ct, returns theta, phi and interiority
+        auto trial = [&](double a, const double* dx, const double* ds, double* tht, double* pht) {
+            hipLaunchKernelGGL(k_trial, dim3(grid_nm(S)), dim3(EB), 0, st, n, m, a, S->x.p, dx, S->s.p, ds,
+                               S->xt.p, S->stt.p);
             OPF_LAUNCH_CHECK();
+            OPF_HIP(hipEventRecord(S->ev[8], st));
             eval_derivs(S->M, OPF_EVAL_F | OPF_EVAL_C, S->xt.p, nullptr, 1.0, S->sc.p, S->sf, S->ft.p, S->ct.p,
                         nullptr, nullptr, nullptr, st);
+            OPF_HIP(hipEventRecord(S->ev[9], st));
             double ft = read_scalar(S, S->ft.p);
+            float tt = 0;
+            OPF_HIP(hipEventElapsedTime(&tt, S->ev[8], S->ev[9]));
+            t_trial += tt;
+            return merit(S, S->xt.p, S->stt.p, S->ct.p, mu, ft, tht, pht);
+        };
+        const int lens[7] = {n, m, m, n, n, m, m};
+        while (true) {
+            nls++;
             double tht, pht;
-            bool inside = merit(S, S->xt.p, S->stt.p, S->ct.p, mu, ft, &tht, &pht);
-            bool ok = false, ftype = false;
-            if (inside && std::isfinite(tht) && std::isfinite(pht) && tht < S->theta_max) {
-                bool filt = true;
-                for (auto& p : S->filter)
-                    if (!(tht < p.first || pht < p.second)) {
-                        filt = false;
-                        break;
-                    }
-                if (filt) {
-                    bool switching = gphi < 0 && alpha * std::pow(-gphi, K.s_phi) > K.delta * std::pow(th0, K.s_theta);
-                    if (th0 <= S->theta_min && switching) {
-                        ok = pht <= ph0 + K.eta_phi * alpha * gphi;
-                        ftype = true;
-                    } else {
-                        ok = tht <= (1.0 - K.gamma_theta) * th0 || pht <= ph0 - K.gamma_phi * th0;
-                    }
-                }
-            }
-            if (ok) {
+            bool inside = trial(alpha, S->d[0].p, S->d[1].p, &tht, &pht);
+            bool ftype = false;
+            if (acceptable(tht, pht, inside, alpha, &ftype)) {
                 accepted = true;
                 augment = !ftype;
                 break;
+            }
+            if (S->o.soc && nls == 1 && !(tht < th0)) {
+                // second-order correction: the same Newton matrix with the constraint residual replaced by the
+                // accumulated c_soc = alpha0 (c - s) + (c_trial - s_trial)
+                const double alpha0 = alpha;
+                for (int q = 0; q < 7; q++)
+                    if (q != 2)
+                        OPF_HIP(hipMemcpyAsync(S->Rs[q].p, S->R0[q].p, lens[q] * 8, hipMemcpyDeviceToDevice, st));
+                // c_soc starts as alpha0 (c - s): k_soc with a = 0 on (c, s) gives c - s, scaled on the next call
+                hipLaunchKernelGGL(k_soc, dim3(ceil_div(m, EB)), dim3(EB), 0, st, m, 0.0, S->c.p, S->s.p,
+                                   S->csoc.p, S->Rs[2].p);
+                hipLaunchKernelGGL(k_soc, dim3(ceil_div(m, EB)), dim3(EB), 0, st, m, alpha0, S->ct.p, S->stt.p,
+                                   S->csoc.p, S->Rs[2].p);
+                OPF_LAUNCH_CHECK();
+                double th_old = tht;
+                for (int p = 1; p <= K.soc_max; p++) {
+                    nsoc++;
+                    refined_solve(S, S->Rs, S->dsoc, I.delta_w);
+                    hipLaunchKernelGGL(red_alpha, dim3(RED_BLOCKS), dim3(EB), 0, st, n, m, V, S->dsoc[0].p,
+                                       S->dsoc[1].p, S->dsoc[3].p, S->dsoc[4].p, S->dsoc[5].p, S->dsoc[6].p, tau,
+                                       S->part.p);
+                    OPF_LAUNCH_CHECK();
+                    double as[2];
+                    finish<2>(S, {MIN, MIN}, as);
+                    double ths, phs;
+                    bool ins = trial(as[0], S->dsoc[0].p, S->dsoc[1].p, &ths, &phs);
+                    bool ft2 = false;
+                    if (acceptable(ths, phs, ins, alpha0, &ft2)) {
+                        for (int q = 0; q < 7; q++)
+                            OPF_HIP(hipMemcpyAsync(S->d[q].p, S->dsoc[q].p, lens[q] * 8, hipMemcpyDeviceToDevice,
+                                                   st));
+                        alpha = as[0];
+                        az = as[1];
+                        accepted = true;
+                        augment = !ft2;
+                        break;
+                    }
+                    if (p == K.soc_max || ths > K.kappa_soc * th_old) break;
+                    hipLaunchKernelGGL(k_soc, dim3(ceil_div(m, EB)), dim3(EB), 0, st, m, as[0], S->ct.p, S->stt.p,
+                                       S->csoc.p, S->Rs[2].p);
+                    OPF_LAUNCH_CHECK();
+                    th_old = ths;
+                }
+                if (accepted) break;
             }
             alpha *= 0.5;
             if (alpha < amin) break;
         }
     }
     I.ls_trials = nls;
+    I.soc_steps = nsoc;
     if (!accepted) {
         if (info) *info = I;
         set_error("ipm_step: line search failed at iteration %d", S->iter);
@@ -923,14 +1043,16 @@ static int ipm_step_impl(ipm_state* S, ipm_iter_info* info) {
                        S->d[0].p, S->d[1].p, S->d[2].p, S->d[3].p, S->d[4].p, S->d[5].p, S->d[6].p);
     OPF_LAUNCH_CHECK();
     OPF_HIP(hipEventRecord(S->ev[7], st));
-    eval_point(S);
+    eval_point(S, S->ev[8]);
     OPF_HIP(hipStreamSynchronize(st));
     I.alpha = alpha;
     I.alpha_z = az;
-    float tad = 0, tsol = 0;
+    float tad = 0, tpt = 0, tsol = 0;
     OPF_HIP(hipEventElapsedTime(&tad, S->ev[0], S->ev[1]));
+    OPF_HIP(hipEventElapsedTime(&tpt, S->ev[7], S->ev[8]));
     OPF_HIP(hipEventElapsedTime(&tsol, S->ev[5], S->ev[6]));
-    I.t_ad = tad;
+    // every derivative evaluation of the iteration: Hessian, trial points, new point (c, J, gradient)
+    I.t_ad = tad + tpt + t_trial;
     I.t_solve = tsol;
     I.t_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     S->iter++;
@@ -947,19 +1069,38 @@ extern "C" int ipm_step(ipm_state* S, ipm_iter_info* info) {
     return rc != OPF_OK ? rc : status;
 }
 
-extern "C" int ipm_solve(ipm_state* S, int32_t* iters, double* obj) {
+extern "C" int ipm_solve(ipm_state* S, ipm_result* out) {
     int status = OPF_OK;
+    ipm_result R{};
     int rc = guarded([&] {
         OPF_CHECK(S, OPF_E_INVALID, "ipm_solve: null state");
+        const auto t0 = std::chrono::steady_clock::now();
         ipm_iter_info I{};
         while (true) {
+            I = ipm_iter_info{};
             status = ipm_step_impl(S, &I);
+            R.factorizations += I.factorizations;
+            R.ir_steps += I.ir_steps;
+            R.t_ad += I.t_ad;
+            R.t_assembly += I.t_assembly;
+            R.t_factor += I.t_factor;
+            R.t_solve += I.t_solve;
             if (status != OPF_OK) break;
         }
-        if (iters) *iters = S->iter;
-        if (obj) *obj = I.obj;
+        R.status = status == 1 ? 1 : status;
+        R.iterations = S->iter;
+        R.objective = I.obj;
+        R.e0 = I.e0;
+        R.inf_pr = I.inf_pr;
+        R.inf_du = I.inf_du;
+        R.t_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        R.x = S->x.p;
+        R.s = S->s.p;
+        R.y = S->y.p;
         if (status == 1) status = OPF_OK;
     });
+    if (rc != OPF_OK) R.status = rc;
+    if (out) *out = R;
     return rc != OPF_OK ? rc : status;
 }
 
@@ -1009,7 +1150,7 @@ extern "C" int ipm_set_state(ipm_state* S, const double* x, const double* s, con
         put(S->vu, vu, S->m);
         S->mu = mu;
         S->dw_last = dw_last;
-        eval_point(S);
+        eval_point(S, nullptr);
         OPF_HIP(hipStreamSynchronize(S->st));
     });
 }

@@ -60,10 +60,150 @@ __global__ __launch_bounds__(KB) void sym_gather_mv(int n, const int32_t* __rest
     out[r] = s;
 }
 
+// ---------------------------------------------------------------- segmented wave gathers
+// Every output of a gather (an entry of K, a row of J x, ...) is the sum of its terms.  The terms are stored
+// sorted by output, 64 to a chunk, so that a wave reads its lanes' term codes with one coalesced load and
+// each lane evaluates one term; the lanes of a chunk are then summed per output by a segmented inclusive
+// scan (six shuffle steps, fixed order), the partial sum of an output that continues into the next chunk
+// is carried to that chunk's lane 0, and the lane holding an output's last term writes it.  Work per wave
+// is balanced by term count, not by output, and the summation order is fixed (bitwise reproducible).
+constexpr int SEG_CPW = 4;  // chunks per wave range (a range is extended to the next output boundary)
+
+// Condensed-assembly term codes (all fields unsigned): a Jacobian pair term J_a D_r J_b packs a (22 bits),
+// b (22 bits), r (20 bits); r = KT_HESS marks a Hessian entry h (44 bits), r = KT_DIAG the diagonal of column
+// c (sigma_x[c] + dw).
+constexpr uint64_t KT_HESS = 0xFFFFF, KT_DIAG = 0xFFFFE, KT_ZERO = 0xFFFFD;  // KT_ZERO: padding, value 0
+
+struct KEval {
+    const double *jac, *dvec, *hess, *sigx;
+    double dw;
+    __device__ __forceinline__ double operator()(uint64_t u) const {
+        const uint64_t r = u >> 44;
+        if (r == KT_HESS) return hess[u & 0xFFFFFFFFFFFull];
+        if (r == KT_DIAG) return sigx[u & 0x3FFFFF] + dw;
+        if (r == KT_ZERO) return 0.0;
+        return jac[u & 0x3FFFFF] * dvec[r] * jac[(u >> 22) & 0x3FFFFF];
+    }
+};
+
+// a[lo 32 bits] * b[hi 32 bits]; the code PROD_ZERO (an output without terms) evaluates to 0
+constexpr uint64_t PROD_ZERO = ~0ull;
+struct ProdEval {
+    const double *a, *b;
+    __device__ __forceinline__ double operator()(uint64_t u) const {
+        return u == PROD_ZERO ? 0.0 : a[(uint32_t)u] * b[(uint32_t)(u >> 32)];
+    }
+};
+
+template <class Eval>
+__global__ __launch_bounds__(KB) void seg_gather(int nwaves, const int32_t* __restrict__ wptr,
+                                                 const uint64_t* __restrict__ term,
+                                                 const uint64_t* __restrict__ smask,
+                                                 const uint64_t* __restrict__ emask,
+                                                 const int32_t* __restrict__ base, Eval ev,
+                                                 const double* __restrict__ add, double* __restrict__ out) {
+    const int w = blockIdx.x * (KB / 64) + threadIdx.x / 64;
+    if (w >= nwaves) return;
+    const int lane = threadIdx.x % 64;
+    const uint64_t below = lane == 63 ? ~0ull : ((2ull << lane) - 1);  // lanes 0..lane
+    double carry = 0.0;
+    for (int c = wptr[w]; c < wptr[w + 1]; c++) {
+        double v = ev(term[(int64_t)c * 64 + lane]);
+        const uint64_t sm = smask[c], em = emask[c];
+        int f = (int)((sm >> lane) & 1);
+        if (lane == 0 && !f) v += carry;  // the output continued from the previous chunk
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const double vp = __shfl_up(v, d);
+            const int fp = __shfl_up(f, d);
+            if (lane >= d) {
+                if (!f) v += vp;
+                f |= fp;
+            }
+        }
+        if ((em >> lane) & 1) {
+            const int o = base[c] + __popcll(sm & below & ~1ull);
+            out[o] = add ? add[o] + v : v;
+        }
+        carry = __shfl(v, 63);
+    }
+}
+
+// Build a SegList from (output, code) pairs already in output order.  Wave ranges are SEG_CPW chunks long and
+// begin at a chunk boundary: an output that would straddle a range boundary is moved to the next range, the
+// gap filled with `zero_code` terms (value 0, no start or end bit), so no output is split between waves
+// except one longer than a whole range, which extends its range.
+void build_seglist(SegList& L, const std::vector<int32_t>& outs, const std::vector<uint64_t>& codes,
+                   uint64_t zero_code, Deferred& dev) {
+    const int64_t n_in = (int64_t)codes.size();
+    const int64_t RW = (int64_t)SEG_CPW * 64;  // terms per range
+    std::vector<uint64_t> term;
+    std::vector<int32_t> tout;     // output of each placed term (-1 for padding)
+    std::vector<char> first, last;  // term starts / ends its output
+    term.reserve(n_in + n_in / 8 + 64);
+    for (int64_t t = 0; t < n_in;) {
+        int64_t u = t;
+        while (u < n_in && outs[u] == outs[t]) u++;  // terms [t, u) form one output
+        const int64_t len = u - t, pos = (int64_t)term.size(), off = pos % RW;
+        if (off != 0 && len <= RW && off + len > RW)
+            for (int64_t q = off; q < RW; q++) {
+                term.push_back(zero_code);
+                tout.push_back(-1);
+                first.push_back(0);
+                last.push_back(0);
+            }
+        for (int64_t q = t; q < u; q++) {
+            term.push_back(codes[q]);
+            tout.push_back(outs[q]);
+            first.push_back(q == t);
+            last.push_back(q == u - 1);
+        }
+        t = u;
+    }
+    const int64_t nt = (int64_t)term.size();
+    const int64_t nch = (nt + 63) / 64;
+    term.resize(nch * 64, zero_code);
+    std::vector<uint64_t> sm(nch, 0), em(nch, 0);
+    std::vector<int32_t> base(nch, 0), wptr{0};
+    for (int64_t t = 0; t < nt; t++) {
+        const int64_t c = t / 64, l = t % 64;
+        if (first[t]) sm[c] |= 1ull << l;
+        if (last[t]) em[c] |= 1ull << l;
+    }
+    // a chunk's base is the output of its lane 0 (padding only ever ends a range, so a chunk is either all
+    // padding, whose base is never used, or starts with a real term)
+    for (int64_t c = 0; c < nch; c++) base[c] = c * 64 < nt && tout[c * 64] >= 0 ? tout[c * 64] : 0;
+    for (int64_t c = 0; c < nch;) {
+        int64_t e = std::min(nch, c + SEG_CPW);
+        while (e < nch && !(sm[e] & 1) && tout[e * 64] >= 0) e++;  // only an output longer than a range
+        wptr.push_back((int32_t)e);
+        c = e;
+    }
+    L.nwaves = (int)wptr.size() - 1;
+    L.nterms = n_in;
+    dev.upload(L.term, term);
+    dev.upload(L.smask, sm);
+    dev.upload(L.emask, em);
+    dev.upload(L.base, base);
+    dev.upload(L.wptr, wptr);
+}
+
+template <class Eval>
+static void run_seg(const SegList& L, Eval ev, const double* add, double* out, hipStream_t s) {
+    if (L.nwaves == 0) return;
+    hipLaunchKernelGGL(seg_gather<Eval>, dim3(ceil_div(L.nwaves, KB / 64)), dim3(KB), 0, s, L.nwaves, L.wptr.p,
+                       L.term.p, L.smask.p, L.emask.p, L.base.p, ev, add, out);
+    OPF_LAUNCH_CHECK();
+}
+
 void condense(const opf_model* M, const double* hess, const double* jac, const double* sigx, const double* dvec,
               double dw, double* kval, hipStream_t s) {
     ensure_device(M);
     if (M->nnzk == 0) return;
+    if (M->seg_k_ok) {
+        run_seg(M->seg_k, KEval{jac, dvec, hess, sigx, dw}, nullptr, kval, s);
+        return;
+    }
     hipLaunchKernelGGL(kkt_gather, dim3(ceil_div(M->nnzk, KB)), dim3(KB), 0, s, M->nnzk, M->k_hptr.p, M->k_hidx.p,
                        M->k_pptr.p, M->k_pa.p, M->k_pb.p, M->k_pr.p, M->k_diag.p, hess, jac, sigx, dvec, dw, kval);
     OPF_LAUNCH_CHECK();
@@ -72,6 +212,10 @@ void condense(const opf_model* M, const double* hess, const double* jac, const d
 void jt_times(const opf_model* M, const double* jac, const double* v, const double* base, double* out,
               hipStream_t s) {
     ensure_device(M);
+    if (M->seg_jtv.nwaves) {
+        run_seg(M->seg_jtv, ProdEval{jac, v}, base, out, s);
+        return;
+    }
     hipLaunchKernelGGL(csr_gather_mv, dim3(ceil_div(M->n, KB)), dim3(KB), 0, s, M->n, M->jt_ptr.p, M->jt_ent.p,
                        M->j_row.p, jac, v, base, out);
     OPF_LAUNCH_CHECK();
@@ -79,6 +223,10 @@ void jt_times(const opf_model* M, const double* jac, const double* v, const doub
 
 void j_times(const opf_model* M, const double* jac, const double* x, double* out, hipStream_t s) {
     ensure_device(M);
+    if (M->seg_jx.nwaves) {
+        run_seg(M->seg_jx, ProdEval{jac, x}, nullptr, out, s);
+        return;
+    }
     hipLaunchKernelGGL(csr_gather_mv, dim3(ceil_div(M->m, KB)), dim3(KB), 0, s, M->m, M->jr_ptr.p, M->jr_ent.p,
                        M->j_col.p, jac, x, (const double*)nullptr, out);
     OPF_LAUNCH_CHECK();
@@ -86,6 +234,10 @@ void j_times(const opf_model* M, const double* jac, const double* x, double* out
 
 void w_times(const opf_model* M, const double* hess, const double* x, double* out, hipStream_t s) {
     ensure_device(M);
+    if (M->seg_wx.nwaves) {
+        run_seg(M->seg_wx, ProdEval{hess, x}, nullptr, out, s);
+        return;
+    }
     hipLaunchKernelGGL(sym_gather_mv, dim3(ceil_div(M->n, KB)), dim3(KB), 0, s, M->n, M->w_ptr.p, M->w_ent.p,
                        M->w_oth.p, hess, x, out);
     OPF_LAUNCH_CHECK();
@@ -209,6 +361,51 @@ void build_kkt_maps(opf_model* M) {
     M->dev.upload(M->w_ptr, wptr);
     M->dev.upload(M->w_ent, went);
     M->dev.upload(M->w_oth, woth);
+
+    if (M->per_entry_assembly) return;
+    // segmented gathers (an output without terms gets one PROD_ZERO term, so every output is written)
+    std::vector<int32_t> outs;
+    std::vector<uint64_t> codes;
+    auto prod_list = [&](SegList& L, int nout, const std::vector<int32_t>& ptr, auto&& code_of) {
+        outs.clear();
+        codes.clear();
+        for (int o = 0; o < nout; o++) {
+            if (ptr[o + 1] == ptr[o]) {
+                outs.push_back(o);
+                codes.push_back(PROD_ZERO);
+            }
+            for (int u = ptr[o]; u < ptr[o + 1]; u++) {
+                outs.push_back(o);
+                codes.push_back(code_of(u));
+            }
+        }
+        build_seglist(L, outs, codes, PROD_ZERO, M->dev);
+    };
+    auto pack = [](int32_t lo, int32_t hi) { return (uint64_t)(uint32_t)lo | ((uint64_t)(uint32_t)hi << 32); };
+    prod_list(M->seg_jx, m, jr_ptr, [&](int u) { return pack(jr_ent[u], M->jcol[jr_ent[u]]); });
+    prod_list(M->seg_jtv, n, jt_ptr, [&](int u) { return pack(jt_ent[u], M->jrow[jt_ent[u]]); });
+    prod_list(M->seg_wx, n, wptr, [&](int u) { return pack(went[u], woth[u]); });
+    M->seg_k_ok = nj < (int64_t(1) << 22) && n < (1 << 22) && m < (int)KT_ZERO && nh < (int64_t(1) << 44);
+    if (M->seg_k_ok) {
+        outs.clear();
+        codes.clear();
+        const int64_t nk = M->nnzk;
+        for (int64_t k = 0; k < nk; k++) {
+            if (kdiag[k] >= 0) {
+                outs.push_back((int32_t)k);
+                codes.push_back((uint64_t)kdiag[k] | (KT_DIAG << 44));
+            }
+            for (int e = hptr[k]; e < hptr[k + 1]; e++) {
+                outs.push_back((int32_t)k);
+                codes.push_back((uint64_t)hidx[e] | (KT_HESS << 44));
+            }
+            for (int e = pptr[k]; e < pptr[k + 1]; e++) {
+                outs.push_back((int32_t)k);
+                codes.push_back((uint64_t)pa[e] | ((uint64_t)pb[e] << 22) | ((uint64_t)pr[e] << 44));
+            }
+        }
+        build_seglist(M->seg_k, outs, codes, KT_ZERO << 44, M->dev);
+    }
 }
 
 }  // namespace opf

@@ -5,6 +5,20 @@
 
 #include "common.h"
 
+namespace opf {
+// Terms of a gather sorted by their output index, for the segmented wave gathers of kkt.hip: 64 terms per
+// chunk (one per lane), a chunk's lanes reduced by a segmented scan, each wave walking a range of chunks that
+// starts at an output boundary.  A term is a 64-bit code interpreted by the gather's evaluator.
+struct SegList {
+    DBuf<uint64_t> term;          // [nchunks * 64]
+    DBuf<uint64_t> smask, emask;  // [nchunks]: bit l set if term l is the first / last term of its output
+    DBuf<int32_t> base;           // [nchunks]: output index of the chunk's first term
+    DBuf<int32_t> wptr;           // [nwaves + 1]: chunk range of each wave
+    int nwaves = 0;
+    int64_t nterms = 0;
+};
+}  // namespace opf
+
 struct opf_model {
     int N = 0, E = 0, G = 0, ref = 0;
     int n = 0, m = 0;
@@ -35,6 +49,10 @@ struct opf_model {
     opf::DBuf<int32_t> jr_ptr, jr_ent;       // CSR: row -> entries
     // symmetric Hessian product: row -> (entry, other index)
     opf::DBuf<int32_t> w_ptr, w_ent, w_oth;
+    // segmented gathers: condensed assembly (when its codes fit: nnz_jac < 2^22, m < 2^20 - 2), J x, J^T v, W x
+    bool per_entry_assembly = false;  // opf_options.assembly == 1: keep the per-entry gather lists only
+    bool seg_k_ok = false;
+    opf::SegList seg_k, seg_jx, seg_jtv, seg_wx;
 
     opf::Deferred dev;  // pending uploads, run at the first device use
 };

@@ -449,9 +449,17 @@ static void build_structure(opf_model* M, const opf_grid* g) {
     M->dev.alloc(M->fpart, 1);
 }
 
-extern "C" int opf_create(const opf_grid* g, opf_model** out) {
+extern "C" void opf_default_options(opf_options* o) {
+    if (o) o->assembly = 0;
+}
+
+extern "C" int opf_create(const opf_grid* g, const opf_options* opts, void* stream, opf_model** out) {
     return guarded([&] {
         OPF_CHECK(g && out, OPF_E_INVALID, "opf_create: null argument");
+        opf_options o{};
+        opf_default_options(&o);
+        if (opts) o = *opts;
+        OPF_CHECK(o.assembly == 0 || o.assembly == 1, OPF_E_INVALID, "opf_create: assembly must be 0 or 1");
         *out = nullptr;
         OPF_CHECK(g->nbus >= 1 && g->nbranch >= 0 && g->ngen >= 1, OPF_E_INVALID,
                   "opf_create: need nbus >= 1, nbranch >= 0, ngen >= 1");
@@ -485,6 +493,8 @@ extern "C" int opf_create(const opf_grid* g, opf_model** out) {
             M->ref = g->ref_bus;
             M->n = (int)(2 * N + 2 * G + 4 * E);
             M->m = (int)(2 * N + 1 + 7 * E);
+            M->dev.stream = (hipStream_t)stream;
+            M->per_entry_assembly = o.assembly == 1;
             build_structure(M, g);
             build_kkt_maps(M);
         } catch (...) {

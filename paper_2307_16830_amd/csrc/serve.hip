@@ -1,15 +1,20 @@
 // Continuous-batching solve server (declared in opf.h).
 //
 // Worker slots, each a host thread with its own non-blocking HIP stream at the default priority, pull
-// requests in arrival order.  One device allocation (the pool) is carved into per-request regions: a slot
-// takes the largest free block as a provisional region, creates the request's model buffers and IPM state
-// inside it (every DBuf of the calling thread is bump-allocated there), keeps exactly what was used (the
-// request's footprint) and returns the rest.  Creation is one slot at a time, so the provisional block is
-// never contended; the solves themselves run concurrently and overlap on the device.  A request that does
-// not fit waits (no further admissions) until a running request returns its region; one that does not fit
-// an empty pool is answered with OPF_E_BUDGET.  Nothing is hipMalloc'ed or hipFree'd while serving, so no
-// request's completion synchronizes the device under the others.
+// requests in arrival order.  A slot first does the request's host work on its own (model structure,
+// symbolic analysis of the condensed pattern), so analyses of different requests run in parallel.  One
+// device allocation (the pool) is carved into per-request regions: at admission a slot takes the largest
+// free block as a provisional region, creates the request's device buffers and IPM state inside it (every
+// DBuf of the calling thread is bump-allocated there), keeps exactly what was used (the request's
+// footprint) and returns the rest.  Admission is one slot at a time, so the provisional block is never
+// contended; the solves themselves run concurrently and overlap on the device.  A request that does not fit
+// waits (no further admissions) until a running request returns its region; one that does not fit an empty
+// pool is answered with OPF_E_BUDGET.  Nothing is hipMalloc'ed, hipFree'd or host-pinned while serving (each
+// slot keeps one pinned scalar buffer and its events for all its requests), so no request's creation or
+// completion synchronizes the device under the others.  With ipm_options.graphs each solve's factorization
+// and triangular solves are captured once on the slot's stream and replayed.
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -25,6 +30,9 @@
 using namespace opf;
 
 int ipm_prepare_device(ipm_state* S);  // ipm.hip: perform every pending device upload of a state now
+// ipm.hip: ipm_create with a prebuilt analysis (ownership passes) and a lent pinned buffer and events
+int ipm_create_ex(opf_model* M, const ipm_options* opts, const chol_options* copts, void* stream, chol_sym* prebuilt,
+                  double* host, const hipEvent_t* events, ipm_state** out);
 
 namespace {
 
@@ -123,10 +131,15 @@ struct opf_server {
     std::unordered_map<int64_t, Done> done;
     std::unordered_set<int64_t> active;  // tags submitted and not finished
     int running = 0;        // admitted, solve not finished
+    int preparing = 0;      // taken from the queue, host phase or waiting for admission
     bool creating = false;  // a slot holds the provisional block
     bool blocked = false;   // the queue head did not fit: admit nothing until memory comes back
     bool stop = false;
     std::vector<hipStream_t> streams;
+    // per slot: a pinned buffer of 16 doubles and 10 events lent to every state the slot creates, so no
+    // request allocates or frees pinned memory or events while others run
+    std::vector<double*> pinned;
+    std::vector<std::array<hipEvent_t, 10>> events;
     std::vector<std::thread> workers;
 };
 
@@ -145,33 +158,59 @@ void worker(opf_server* S, int slot) {
     hipStream_t st = S->streams[slot];
     std::unique_lock<std::mutex> lk(S->mu);
     while (true) {
-        S->cv_work.wait(lk, [&] { return (S->stop && S->queue.empty()) || (!S->queue.empty() && !S->creating && !S->blocked); });
+        S->cv_work.wait(lk, [&] { return (S->stop && S->queue.empty()) || (!S->queue.empty() && !S->blocked); });
         if (S->queue.empty()) break;
         Request rq = std::move(S->queue.front());
         S->queue.pop_front();
-        const auto blk = S->regions.largest();
-        if (blk.second) S->regions.take(blk.first);
-        S->creating = true;
-        const bool alone = S->running == 0;  // then the block is the whole pool
+        S->preparing++;
         lk.unlock();
 
+        // host phase, outside admission: model structure (if rebuilt) and the symbolic analysis; device
+        // buffers of both are deferred, so they are carved from the pool block at admission
         Done d;
         d.r.tag = rq.tag;
         d.r.t_submit = rq.t_submit;
         int rc = OPF_OK;
-        if (!rq.model) rc = opf_create(&rq.grid->g, &rq.model);
+        if (!rq.model) rc = opf_create(&rq.grid->g, nullptr, st, &rq.model);
         if (rc == OPF_OK) {
             int64_t a, b, c;
             rc = opf_dims(rq.model, &d.r.n, &d.r.m, &a, &b, &c);
         }
+        chol_sym* sym = nullptr;
+        if (rc == OPF_OK) {
+            std::vector<int32_t> cp(d.r.n + 1), ri;
+            int64_t nj, nh, nk;
+            int32_t n2, m2;
+            rc = opf_dims(rq.model, &n2, &m2, &nj, &nh, &nk);
+            if (rc == OPF_OK) {
+                ri.resize(nk);
+                rc = kkt_pattern(rq.model, cp.data(), ri.data());
+            }
+            if (rc == OPF_OK) rc = chol_analyze(d.r.n, cp.data(), ri.data(), &S->o.chol, &sym);
+        }
+
+        // admission: one slot at a time takes the largest free block, creates the state inside it and keeps
+        // only what it used
+        lk.lock();
+        S->cv_work.wait(lk, [&] { return !S->creating; });
+        const auto blk = S->regions.largest();
+        if (blk.second) S->regions.take(blk.first);
+        S->creating = true;
+        S->preparing--;
+        const bool alone = S->running == 0;  // then the block is the whole pool
+        lk.unlock();
+
         ipm_state* state = nullptr;
         DeviceRegion reg{S->pool + blk.first, blk.second, 0};
         if (rc == OPF_OK) {
             thread_region() = &reg;
-            rc = ipm_create(rq.model, &S->o.ipm, &S->o.chol, st, &state);
+            rc = ipm_create_ex(rq.model, &S->o.ipm, &S->o.chol, st, sym, S->pinned[slot], S->events[slot].data(),
+                               &state);
+            sym = nullptr;  // owned by the state (or freed by the failed creation)
             if (rc == OPF_OK) rc = ipm_prepare_device(state);
             thread_region() = nullptr;
         }
+        if (sym) chol_destroy(sym);
         const size_t used = align_up(reg.used);
         if (rc != OPF_OK) {
             // nothing of this request may touch the block once it is returned
@@ -205,12 +244,11 @@ void worker(opf_server* S, int slot) {
 
         d.r.footprint = (int64_t)used;
         d.r.t_admit = now_s();
-        int32_t it = 0;
-        double obj = 0;
-        rc = ipm_solve(state, &it, &obj);
+        ipm_result res{};
+        rc = ipm_solve(state, &res);
         d.r.status = rc == OPF_OK ? 1 : rc;
-        d.r.iterations = it;
-        d.r.objective = obj;
+        d.r.iterations = res.iterations;
+        d.r.objective = res.objective;
         d.x.assign(d.r.n, 0.0);
         if (ipm_get_iterate(state, d.x.data(), nullptr, nullptr) != OPF_OK && d.r.status == 1) d.r.status = OPF_E_DEVICE;
         (void)hipStreamSynchronize(st);
@@ -257,15 +295,29 @@ extern "C" int opf_serve_create(const serve_options* o, opf_server** out) {
             throw Error{OPF_E_NOMEM};
         }
         S->regions.init(S->cap);
+        auto cleanup = [&] {
+            for (hipStream_t q : S->streams) (void)hipStreamDestroy(q);
+            for (double* p : S->pinned) (void)hipHostFree(p);
+            for (auto& ev : S->events)
+                for (hipEvent_t e : ev)
+                    if (e) (void)hipEventDestroy(e);
+            (void)hipFree(S->pool);
+        };
         for (int k = 0; k < S->o.slots; k++) {
             hipStream_t s = nullptr;
-            if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
-                for (hipStream_t q : S->streams) (void)hipStreamDestroy(q);
-                (void)hipFree(S->pool);
-                set_error("opf_serve_create: stream creation failed");
+            double* pin = nullptr;
+            std::array<hipEvent_t, 10> ev{};
+            bool ok = hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
+            if (ok) S->streams.push_back(s);
+            ok = ok && hipHostMalloc((void**)&pin, 16 * sizeof(double)) == hipSuccess;
+            if (ok) S->pinned.push_back(pin);
+            for (auto& e : ev) ok = ok && hipEventCreate(&e) == hipSuccess;
+            S->events.push_back(ev);
+            if (!ok) {
+                cleanup();
+                set_error("opf_serve_create: stream, pinned buffer or event creation failed");
                 throw Error{OPF_E_DEVICE};
             }
-            S->streams.push_back(s);
         }
         opf_server* raw = S.release();
         for (int k = 0; k < raw->o.slots; k++) raw->workers.emplace_back(worker, raw, k);
@@ -280,7 +332,7 @@ extern "C" int opf_serve_submit(opf_server* S, const opf_grid* grid, int64_t tag
         rq.tag = tag;
         rq.t_submit = now_s();
         rq.grid = std::make_shared<GridCopy>(*grid);
-        int rc = opf_create(&rq.grid->g, &rq.model);  // host structure only; device uploads wait for admission
+        int rc = opf_create(&rq.grid->g, nullptr, nullptr, &rq.model);  // host structure only; uploads wait for admission
         if (rc != OPF_OK) throw Error{rc};
         std::lock_guard<std::mutex> lk(S->mu);
         if (S->done.count(tag) || S->active.count(tag)) {
@@ -299,7 +351,8 @@ extern "C" int opf_serve_poll(opf_server* S, serve_result* out, int32_t max, int
         std::unique_lock<std::mutex> lk(S->mu);
         if (wait)
             S->cv_done.wait(lk, [&] {
-                return !S->ready.empty() || (S->queue.empty() && S->running == 0 && !S->creating);
+                return !S->ready.empty() ||
+                       (S->queue.empty() && S->running == 0 && !S->creating && S->preparing == 0);
             });
         int k = 0;
         while (k < max && !S->ready.empty()) {
@@ -331,7 +384,7 @@ extern "C" int opf_serve_stats(const opf_server* S, int64_t* in_use, int64_t* pe
         if (in_use) *in_use = (int64_t)M->in_use;
         if (peak_in_use) *peak_in_use = (int64_t)M->peak;
         if (running) *running = M->running + (M->creating ? 1 : 0);
-        if (queued) *queued = (int32_t)M->queue.size();
+        if (queued) *queued = (int32_t)M->queue.size() + M->preparing;
     });
 }
 
@@ -344,6 +397,10 @@ extern "C" int opf_serve_destroy(opf_server* S) {
     }
     for (auto& t : S->workers) t.join();
     for (hipStream_t s : S->streams) (void)hipStreamDestroy(s);
+    for (double* p : S->pinned) (void)hipHostFree(p);
+    for (auto& ev : S->events)
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
     if (S->pool) (void)hipFree(S->pool);
     delete S;
     return OPF_OK;

@@ -25,7 +25,7 @@ OK, E_INVALID, E_NOMEM, E_DEVICE, E_STATE, E_NOT_PD, E_MAXITER, E_LINESEARCH, E_
     0, -1, -2, -3, -4, -5, -6, -7, -8, -9
 EVAL_F, EVAL_C, EVAL_GRAD, EVAL_JAC, EVAL_HESS = 1, 2, 4, 8, 16
 EXPORTED = [
-    "opf_last_error", "opf_create", "opf_destroy", "opf_dims", "opf_structure", "opf_bounds", "opf_initial_point",
+    "opf_last_error", "opf_default_options", "opf_create", "opf_destroy", "opf_dims", "opf_structure", "opf_bounds", "opf_initial_point",
     "opf_eval_derivs", "kkt_pattern", "kkt_condense", "chol_default_options", "chol_analyze", "chol_destroy",
     "chol_info", "chol_perm", "chol_etree", "chol_supernodes", "chol_supernode_rows", "chol_factor", "chol_solve",
     "chol_export_factor", "ipm_default_options", "ipm_create", "ipm_destroy", "ipm_step", "ipm_solve",
@@ -49,15 +49,31 @@ class GridC(ctypes.Structure):
                [("gbus", I32P)] + [(k, F64P) for k in ("c2", "c1", "c0", "pmin", "pmax", "qmin", "qmax")]
 
 
+class OpfOptions(ctypes.Structure):
+    _fields_ = [("assembly", ctypes.c_int32)]
+
+
+class IpmResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iterations", ctypes.c_int32)] + \
+               [(k, ctypes.c_double) for k in ("objective", "e0", "inf_pr", "inf_du")] + \
+               [("factorizations", ctypes.c_int32), ("ir_steps", ctypes.c_int32)] + \
+               [(k, ctypes.c_double) for k in ("t_ad", "t_assembly", "t_factor", "t_solve", "t_total")] + \
+               [("x", VP), ("s", VP), ("y", VP)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k not in ("x", "s", "y")}
+
+
 class CholOptions(ctypes.Structure):
     _fields_ = [("dense_frac", ctypes.c_double), ("dense_abs", ctypes.c_int32), ("max_width", ctypes.c_int32),
-                ("zero_abs", ctypes.c_int64), ("zero_rel", ctypes.c_double), ("pivot_tol", ctypes.c_double)]
+                ("zero_abs", ctypes.c_int64), ("zero_rel", ctypes.c_double), ("pivot_tol", ctypes.c_double),
+                ("tile_min", ctypes.c_int32), ("pair_min", ctypes.c_int32)]
 
 
 class IpmOptions(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("max_ir", ctypes.c_int32),
                 ("ir_tol", ctypes.c_double), ("mu_init", ctypes.c_double), ("bound_relax", ctypes.c_double),
-                ("pivot_tol", ctypes.c_double)]
+                ("pivot_tol", ctypes.c_double), ("graphs", ctypes.c_int32), ("soc", ctypes.c_int32)]
 
 
 class ServeOptions(ctypes.Structure):
@@ -80,7 +96,8 @@ class IterInfo(ctypes.Structure):
                                              ("obj", "e0", "inf_pr", "inf_du", "mu", "delta_w", "alpha",
                                               "alpha_z")] + \
                [(k, ctypes.c_int32) for k in ("ls_trials", "ir_steps", "factorizations")] + \
-               [(k, ctypes.c_double) for k in ("t_ad", "t_assembly", "t_factor", "t_solve", "t_total")]
+               [(k, ctypes.c_double) for k in ("t_ad", "t_assembly", "t_factor", "t_solve", "t_total")] + \
+               [("soc_steps", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -96,7 +113,9 @@ def lib():
             raise ImportError(f"{LIB_PATH} is missing: build it with paper_2307_16830_amd.build.build()")
         L = ctypes.CDLL(LIB_PATH)
         L.opf_last_error.restype = ctypes.c_char_p
-        L.opf_create.argtypes = [ctypes.POINTER(GridC), ctypes.POINTER(VP)]
+        L.opf_default_options.argtypes = [ctypes.POINTER(OpfOptions)]
+        L.opf_default_options.restype = None
+        L.opf_create.argtypes = [ctypes.POINTER(GridC), ctypes.POINTER(OpfOptions), VP, ctypes.POINTER(VP)]
         L.opf_destroy.argtypes = [VP]
         L.opf_dims.argtypes = [VP, I32P, I32P, I64P, I64P, I64P]
         L.opf_structure.argtypes = [VP, I32P, I32P, I32P, I32P]
@@ -124,7 +143,7 @@ def lib():
         L.ipm_create.argtypes = [VP, ctypes.POINTER(IpmOptions), ctypes.POINTER(CholOptions), VP, ctypes.POINTER(VP)]
         L.ipm_destroy.argtypes = [VP]
         L.ipm_step.argtypes = [VP, ctypes.POINTER(IterInfo)]
-        L.ipm_solve.argtypes = [VP, I32P, F64P]
+        L.ipm_solve.argtypes = [VP, ctypes.POINTER(IpmResult)]
         L.ipm_get_iterate.argtypes = [VP, F64P, F64P, F64P]
         L.ipm_chol.argtypes = [VP]
         L.ipm_chol.restype = VP
@@ -206,11 +225,17 @@ def _grid_struct(grid, keep):
 class Model:
     """An ACOPF instance on the device (wraps ``opf_model``)."""
 
-    def __init__(self, grid):
+    def __init__(self, grid, assembly=0, stream=None):
         self._keep = {}
         g = _grid_struct(grid, self._keep)
+        o = OpfOptions()
+        lib().opf_default_options(ctypes.byref(o))
+        o.assembly = int(assembly)
         h = VP()
-        _check(lib().opf_create(ctypes.byref(g), ctypes.byref(h)), "opf_create")
+        # the uploads run at the model's first device use, on `stream` (None: the null stream, so that host-only
+        # queries never touch the GPU)
+        st = ctypes.c_void_p(stream) if stream is not None else None
+        _check(lib().opf_create(ctypes.byref(g), ctypes.byref(o), st, ctypes.byref(h)), "opf_create")
         self._h = h
         self._keep = None
         n, m = ctypes.c_int32(), ctypes.c_int32()
@@ -334,22 +359,23 @@ class Cholesky:
         _check(lib().chol_solve(self._h, _dptr(b), _dptr(x), nrhs, _stream(stream)), "chol_solve")
         return x
 
-    TIMING_CATEGORIES = ("assembly", "small_fronts", "diag_block", "panel_solve", "trailing_update")
+    TIMING_CATEGORIES = ("assembly", "small_fronts", "diag_block", "panel_solve", "trailing_update", "dense_front")
 
     def timing(self, categories=True):
         """Bracket the launches of the given categories (names from TIMING_CATEGORIES, or a bit mask;
         empty / 0 disables) with HIP events; resets the totals."""
         if isinstance(categories, (int, bool)):
-            mask = 31 if categories is True else int(categories)
+            mask = (1 << len(self.TIMING_CATEGORIES)) - 1 if categories is True else int(categories)
         else:
             mask = sum(1 << self.TIMING_CATEGORIES.index(c) for c in categories)
         _check(lib().chol_timing(self._h, mask), "chol_timing")
 
     def timing_read(self):
-        ms = np.zeros(5)
-        nl = np.zeros(5, np.int64)
-        fl = np.zeros(5)
-        by = np.zeros(5)
+        nc = len(self.TIMING_CATEGORIES)
+        ms = np.zeros(nc)
+        nl = np.zeros(nc, np.int64)
+        fl = np.zeros(nc)
+        by = np.zeros(nc)
         _check(lib().chol_timing_read(self._h, _p(ms, F64P), _p(nl, I64P), _p(fl, F64P), _p(by, F64P)),
                "chol_timing_read")
         return {k: {"ms": ms[i], "launches": int(nl[i]), "flops": fl[i], "bytes": by[i]}
@@ -397,12 +423,14 @@ class IPM:
         return rc, d
 
     def solve(self):
-        it = ctypes.c_int32()
-        obj = ctypes.c_double()
-        rc = lib().ipm_solve(self._h, ctypes.byref(it), ctypes.byref(obj))
+        """Algorithm 1 to convergence: (status, iterations, objective); the whole ``ipm_result`` (totals, stage
+        times, final optimality error) is left in ``self.result``."""
+        r = IpmResult()
+        rc = lib().ipm_solve(self._h, ctypes.byref(r))
+        self.result = r.as_dict()
         if rc < 0 and rc not in (E_MAXITER, E_LINESEARCH, E_NUMERIC, E_NOT_PD):
             _check(rc, "ipm_solve")
-        return rc, it.value, obj.value
+        return rc, r.iterations, r.objective
 
     def get_state(self):
         n, m = self.model.n, self.model.m

@@ -36,3 +36,17 @@ def random_point(model, rng, spread=0.2):
     x[L.op:L.op + 2 * L.E] = rng.uniform(-1, 1, 2 * L.E)
     x[L.oq:L.oq + 2 * L.E] = rng.uniform(-1, 1, 2 * L.E)
     return x
+
+
+_CONFIG_CACHE = {}
+
+
+def config_grid(name):
+    """Generated benchmark grid by configuration name, generated once per test session (the 10k- and 80k-bus
+    feasibility repairs take tens of seconds); every call returns a private copy."""
+    import copy
+
+    from paper_2307_16830_amd import gridgen
+    if name not in _CONFIG_CACHE:
+        _CONFIG_CACHE[name] = gridgen.make_config(name)
+    return copy.deepcopy(_CONFIG_CACHE[name])

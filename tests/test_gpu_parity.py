@@ -14,6 +14,7 @@ from oracle import ipm as oipm
 from oracle import kkt as okkt
 from oracle.model import Model as OModel, canonical
 from paper_2307_16830_amd import gridgen
+from tests._grids import config_grid
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -44,7 +45,7 @@ def host(t):
 
 def grid_for(name):
     if name in gridgen.CONFIGS:
-        return gridgen.make_config(name)
+        return config_grid(name)
     N, E, G, seed = name
     return gridgen.make_grid(N, E, G, seed)
 
@@ -263,16 +264,18 @@ def test_ipm_cfg0_matches_oracle(seed):
     assert abs(obj - I.model.objective(I.x)) <= 1e-6 * abs(obj)
 
 
-@pytest.mark.parametrize("n", [65, 100, 200, 333])
+@pytest.mark.parametrize("n", [65, 100, 200, 333, 768, 900, 1100, 1300])
 def test_dense_front_blocked_cholesky(n):
-    """A dense SPD matrix is one supernode: exercises the blocked path (LDS diagonal block, panel solve, MFMA update)."""
+    """A dense SPD matrix is one supernode: exercises the blocked path (LDS diagonal block, panel solve, MFMA
+    update), up to fronts of 1,300 pivots; with pair_min = 1,024 a lone front from that size pairs its panels
+    (rank-128 trailing updates), 1,100 ending on a partial pair and 1,300 on an unpaired panel."""
     rng = np.random.default_rng(n)
     A = rng.normal(size=(n, n))
     K = A @ A.T + n * np.eye(n)
     rows, cols = np.tril_indices(n)
     cp, ri = ochol.lower_csc(n, rows, cols)
     colidx = np.repeat(np.arange(n), np.diff(cp))
-    C = opf().Cholesky(n, cp, ri)
+    C = opf().Cholesky(n, cp, ri, opf().chol_options(pair_min=1024))
     assert C.nsuper == 1
     assert C.factor(dev(K[ri, colidx])) == -1
     lp, li, lx = C.export_factor()
@@ -304,14 +307,15 @@ def _block_system(a, b, c, seed):
     return A, cp, ri, A[ri, colidx]
 
 
-@pytest.mark.parametrize("sizes", [(333, 0, 0), (1000, 0, 0), (300, 280, 12), (260, 300, 70), (320, 257, 65)])
+@pytest.mark.parametrize("sizes", [(333, 0, 0), (1000, 0, 0), (300, 280, 12), (260, 300, 70), (320, 257, 65),
+                                   (800, 790, 100), (1100, 1050, 90)])
 def test_wide_front_solves_match_oracle(sizes):
     """Fronts with >= 256 pivots (with and without rows below them) go through the sync-free block
     solves; the solution must match the oracle's factor-and-solve on the same matrix."""
     A, cp, ri, vals = _block_system(*sizes, seed=sum(sizes))
     n = A.shape[0]
     o = dict(OPTS, dense_frac=1.0)
-    C = opf().Cholesky(n, cp, ri, opf().chol_options(**o))
+    C = opf().Cholesky(n, cp, ri, opf().chol_options(**o, pair_min=1024 if n > 2000 else 0))
     rp, rows = C.supernode_rows()
     sp = C.supernodes()
     widths = np.diff(sp)
@@ -359,3 +363,23 @@ def test_newton_direction_matches_oracle(case, tol, iters):
     assert dwg == dwo
     errs = [np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300) for a, b in zip(dg, do)]
     assert max(errs) <= 1e-6, errs
+
+
+@pytest.mark.skip(reason="the dependency-driven tile factorization (chol_options.tile_min) did not finish on its "
+                         "first device run on this 768-column front; it stays off until the cause is shown")
+@pytest.mark.parametrize("n", [768, 1300])
+def test_tile_path_dense_front(n):
+    rng = np.random.default_rng(n)
+    A = rng.normal(size=(n, n))
+    K = A @ A.T + n * np.eye(n)
+    rows, cols = np.tril_indices(n)
+    cp, ri = ochol.lower_csc(n, rows, cols)
+    colidx = np.repeat(np.arange(n), np.diff(cp))
+    C = opf().Cholesky(n, cp, ri, opf().chol_options(**OPTS, tile_min=768))
+    assert C.factor(dev(K[ri, colidx])) == -1
+    lp, li, lx = C.export_factor()
+    L = np.zeros((n, n))
+    for j in range(n):
+        L[li[lp[j]:lp[j + 1]], j] = lx[lp[j]:lp[j + 1]]
+    Lref = np.linalg.cholesky(K)
+    assert np.max(np.abs(L - Lref)) <= 1e-12 * np.max(np.abs(Lref))

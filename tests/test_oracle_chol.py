@@ -1,4 +1,6 @@
 """Pins of the oracle's ordering, symbolic analysis and Cholesky against brute force and dense linear algebra."""
+import math
+
 import numpy as np
 import pytest
 
@@ -203,3 +205,58 @@ def test_not_positive_definite_reports_column():
     ch = ochol.Cholesky(n, cp, ri, sym.perm)
     bad = ch.factor(vals)
     assert bad >= 0 and sym.perm[bad] == 2
+
+
+def _threshold_matrix(frac):
+    """3x3 matrix whose pivot for original column 1 is frac * K_11 exactly in real arithmetic:
+    K = [[1, b, 0], [b, c, 0], [0, 0, 1e14]] with c = 1e12 and b^2 = c (1 - frac).  Column 2 is isolated, so
+    minimum degree eliminates it first; the threshold pivot is the last one.  K_22 is the largest entry, so
+    a threshold taken relative to max |K| instead of K_11 decides differently."""
+    c = 1e12
+    b = math.sqrt(c * (1.0 - frac))
+    n = 3
+    rows = np.array([0, 1, 1, 2])
+    cols = np.array([0, 0, 1, 2])
+    cp, ri = ochol.lower_csc(n, rows, cols)
+    dense = np.array([[1.0, b, 0.0], [b, c, 0.0], [0.0, 0.0, 1e14]])
+    colidx = np.repeat(np.arange(n), np.diff(cp))
+    return n, cp, ri, dense[ri, colidx], dense
+
+
+@pytest.mark.parametrize("frac,tol,rejected", [
+    (5e-13, 1e-12, True),    # pivot 0.5 < 1e-12 * K_11 = 1: sign within rounding noise, rejected
+    (5e-13, 0.0, False),     # textbook rule: positive, accepted
+    (5e-13, 1e-13, False),   # 0.5 > 0.1
+    (3e-12, 1e-12, False),   # 3 > 1
+])
+def test_pivot_threshold_is_relative_to_assembled_diagonal(frac, tol, rejected):
+    """Pins the pivot acceptance rule d_j > tol * |K_jj| (Algorithm 1's inertia test on the condensed matrix):
+    a comparison against L's diagonal (sqrt(d) ~ 0.7), against K_jj before the update, or against the
+    largest entry of K would decide these cases differently."""
+    n, cp, ri, vals, dense = _threshold_matrix(frac)
+    sym = ochol.analyze(n, cp, ri)
+    assert list(sym.perm) == [2, 0, 1]
+    ch = ochol.Cholesky(n, cp, ri, sym.perm)
+    bad = ch.factor(vals, piv_tol=tol)
+    if rejected:
+        assert bad == 2 and sym.perm[bad] == 1
+    else:
+        assert bad == -1
+        lp, li, lx = ch.export()
+        Ld = np.zeros((n, n))
+        for j in range(n):
+            Ld[li[lp[j]:lp[j + 1]], j] = lx[lp[j]:lp[j + 1]]
+        # the accepted pivot is the Schur complement c - b^2 (exact up to the rounding of b^2)
+        assert Ld[2, 2] ** 2 == pytest.approx(frac * 1e12, rel=1e-3)
+
+
+def test_pivot_threshold_rejects_large_negative_pivot():
+    """A pivot of large magnitude but negative sign is rejected at any tolerance (|d| must not be used)."""
+    n = 2
+    cp, ri = ochol.lower_csc(n, np.arange(n), np.arange(n))
+    vals = np.array([1.0, -5.0])
+    sym = ochol.analyze(n, cp, ri)
+    ch = ochol.Cholesky(n, cp, ri, sym.perm)
+    for tol in (0.0, 1e-12):
+        bad = ch.factor(vals, piv_tol=tol)
+        assert bad >= 0 and sym.perm[bad] == 1
