@@ -200,6 +200,23 @@ int chol_factor(chol_sym* sym, const double* kval, void* stream, int32_t* bad_co
  * work-groups that wait on each other's ready flags with a bounded spin, and
  * a wait that ran out (never expected) is reported as OPF_E_DEVICE. */
 int chol_solve(chol_sym* sym, const double* b, double* x, int32_t nrhs, void* stream);
+/* chol_solve for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and the same result as chol_solve, but the solve's working
+ * vectors, the wide-front exchange blocks and the fault word live in one
+ * static device array of 64 MiB per GPU instead of the handle's buffers, and
+ * the call makes no hipMalloc/hipFree or other allocating call.  The array is
+ * resolved to its device address once per device, on the first call with
+ * that device current, and is held until the process ends.  b, x: device
+ * [n*nrhs] as for chol_solve (x may alias b).  Returns OPF_E_INVALID, with a
+ * message giving the bytes needed, when the factor needs more than 64 MiB of
+ * solve scratch (8 bytes per row, per row-structure entry, per update row
+ * and per wide-front row, about 40 MB at 80k buses); OPF_E_STATE without a
+ * successful factorization; OPF_E_DEVICE if a wide-front wait ran out.  All
+ * calls on one GPU share the array: calls that overlap in time on one GPU
+ * (different host threads or streams) race and must be serialized by the
+ * caller.  Synchronizes the stream before returning, like chol_solve. */
+int chol_solve_noalloc(chol_sym* sym, const double* b, double* x, int32_t nrhs, void* stream);
 /* Kernel timing of the numeric factorizations (measurement aid).  `mask`
  * selects categories by bit: 1 assembly, 2 small fronts, 4 diagonal-block
  * Cholesky, 8 panel solve, 16 trailing MFMA update, 32 dense-front tile

@@ -26,6 +26,7 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <mutex>
 
 #include "model.h"
 #include "symbolic.h"
@@ -1983,6 +1984,10 @@ static int read_fault(const chol_sym* C, const int32_t* fault, hipStream_t st) {
 
 int chol_solve_fault(chol_sym* C, hipStream_t st) { return read_fault(C, C->sfault.p, st); }
 
+__global__ void fill_i32(int n, int32_t v, int32_t* __restrict__ p) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
 
 }  // namespace opf
 
@@ -2006,6 +2011,64 @@ extern "C" int chol_solve(chol_sym* C, const double* b, double* x, int32_t nrhs,
             chol_solve_enqueue(C, b + (int64_t)r * C->n, x + (int64_t)r * C->n, (hipStream_t)stream);
         OPF_CHECK(chol_solve_fault(C, (hipStream_t)stream) == 0, OPF_E_DEVICE,
                   "chol_solve: a wide-front block wait exceeded its bound");
+    });
+}
+
+// ---------------------------------------------------------------- allocation-free solve
+// Scratch of chol_solve_noalloc: one static device array per GPU, resolved to a device address once per
+// device with hipGetSymbolAddress (the array's name is only a host-side stand-in).  Layout, each part
+// 256-byte aligned: fault word, y [n], work [row-structure entries], upd [update rows], zx [wide blocks].
+static constexpr size_t SOLVE_SCRATCH_BYTES = size_t(64) << 20;
+static constexpr int MAX_DEVICES = 64;
+static __device__ __align__(256) unsigned char scratch[SOLVE_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[MAX_DEVICES] = {};
+
+static void* scratch_address() {
+    int dev = -1;
+    OPF_HIP(hipGetDevice(&dev));
+    OPF_CHECK(dev >= 0 && dev < MAX_DEVICES, OPF_E_DEVICE, "chol_solve_noalloc: device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        OPF_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        OPF_CHECK(p != nullptr, OPF_E_DEVICE, "chol_solve_noalloc: no device address for the scratch array");
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+
+static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+extern "C" int chol_solve_noalloc(chol_sym* C, const double* b, double* x, int32_t nrhs, void* stream) {
+    return guarded([&] {
+        OPF_CHECK(C && b && x && nrhs >= 0, OPF_E_INVALID, "chol_solve_noalloc: bad argument");
+        const int ns = C->S.nsuper;
+        int64_t nflags = 0;
+        for (int s = 0; s < ns; s++)
+            if (C->h_flag_off[s] >= 0) nflags += (C->h_ncol[s] + SB - 1) / SB;
+        const size_t o_y = 256;
+        const size_t o_work = o_y + align256((size_t)C->n * 8);
+        const size_t o_upd = o_work + align256((size_t)C->h_roff[ns] * 8);
+        const size_t o_zx = o_upd + align256((size_t)C->upd_total * 8);
+        const size_t need = o_zx + align256((size_t)nflags * SB * 8);
+        OPF_CHECK(need <= SOLVE_SCRATCH_BYTES, OPF_E_INVALID,
+                  "chol_solve_noalloc: this factor needs %zu bytes of solve scratch, more than the %zu available "
+                  "(use chol_solve)", need, SOLVE_SCRATCH_BYTES);
+        OPF_CHECK(C->factored, OPF_E_STATE, "chol_solve_noalloc: no successful factorization");
+        char* base = static_cast<char*>(scratch_address());
+        SolveBufs B{reinterpret_cast<double*>(base + o_y), reinterpret_cast<double*>(base + o_work),
+                    reinterpret_cast<double*>(base + o_upd), reinterpret_cast<double*>(base + o_zx),
+                    reinterpret_cast<int32_t*>(base)};
+        hipStream_t st = (hipStream_t)stream;
+        // the array keeps the previous call's contents: the fault word must start at zero (the exchange
+        // blocks are refilled with their sentinel before every sweep inside the solve)
+        hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, st, 1, 0, B.fault);
+        OPF_LAUNCH_CHECK();
+        for (int r = 0; r < nrhs; r++)
+            solve_enqueue(C, b + (int64_t)r * C->n, x + (int64_t)r * C->n, st, B);
+        OPF_CHECK(read_fault(C, B.fault, st) == 0, OPF_E_DEVICE,
+                  "chol_solve_noalloc: a wide-front block wait exceeded its bound");
     });
 }
 

@@ -28,6 +28,7 @@ EXPORTED = [
     "opf_last_error", "opf_default_options", "opf_create", "opf_destroy", "opf_dims", "opf_structure", "opf_bounds", "opf_initial_point",
     "opf_eval_derivs", "kkt_pattern", "kkt_condense", "chol_default_options", "chol_analyze", "chol_destroy",
     "chol_info", "chol_perm", "chol_etree", "chol_supernodes", "chol_supernode_rows", "chol_factor", "chol_solve",
+    "chol_solve_noalloc",
     "chol_export_factor", "ipm_default_options", "ipm_create", "ipm_destroy", "ipm_step", "ipm_solve",
     "ipm_get_iterate", "ipm_chol", "ipm_get_state", "ipm_set_state", "ipm_direction", "chol_timing",
     "chol_timing_read", "serve_default_options", "opf_serve_create", "opf_serve_submit", "opf_serve_poll",
@@ -135,6 +136,7 @@ def lib():
         L.chol_supernode_rows.argtypes = [VP, I64P, I32P]
         L.chol_factor.argtypes = [VP, VP, VP, I32P]
         L.chol_solve.argtypes = [VP, VP, VP, ctypes.c_int32, VP]
+        L.chol_solve_noalloc.argtypes = [VP, VP, VP, ctypes.c_int32, VP]
         L.chol_export_factor.argtypes = [VP, I64P, I32P, F64P]
         L.chol_timing.argtypes = [VP, ctypes.c_int]
         L.chol_timing_read.argtypes = [VP, F64P, I64P, F64P, F64P]
@@ -357,6 +359,13 @@ class Cholesky:
             x = torch.empty_like(b)
         nrhs = 1 if b.dim() == 1 else b.shape[1]
         _check(lib().chol_solve(self._h, _dptr(b), _dptr(x), nrhs, _stream(stream)), "chol_solve")
+        return x
+
+    def solve_noalloc(self, b, x, stream=None):
+        """``chol_solve_noalloc``: the same solve with the library's static per-GPU scratch (no allocation);
+        ``x`` must be given."""
+        nrhs = 1 if b.dim() == 1 else b.shape[1]
+        _check(lib().chol_solve_noalloc(self._h, _dptr(b), _dptr(x), nrhs, _stream(stream)), "chol_solve_noalloc")
         return x
 
     TIMING_CATEGORIES = ("assembly", "small_fronts", "diag_block", "panel_solve", "trailing_update", "dense_front")
