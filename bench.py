@@ -81,6 +81,18 @@ def pct(v, q):
     return float(np.percentile(np.asarray(v), q)) if len(v) else None
 
 
+def tune_serving(grids, nsample=6):
+    """Autotuned factorization options for the serving trace: candidates timed on a sample of its requests
+    spread over the size range (see paper_2307_16830_amd.autotune)."""
+    from paper_2307_16830_amd import autotune, opf
+    order = sorted(range(len(grids)), key=lambda k: grids[k][1].nbus)
+    pick = [order[int(round(q * (len(order) - 1) / max(nsample - 1, 1)))] for q in range(nsample)]
+    models = [opf.Model(grids[k][1]) for k in pick]
+    best, best_dict, table = autotune.tune(models, log=log)
+    return best, {"chosen": best_dict, "sample_buses": [int(grids[k][1].nbus) for k in pick],
+                  "candidates": table}
+
+
 def serving_bench(grids, slots, rate_factor):
     """Continuous-batching server vs one-at-a-time solves on the same GPU and the same requests.
 
@@ -91,9 +103,11 @@ def serving_bench(grids, slots, rate_factor):
     import torch
     from paper_2307_16830_amd import gridgen, opf
 
+    copts, tuning = tune_serving(grids)
+
     def alone(g):
         M = opf.Model(g)
-        ipm = opf.IPM(M, tol=1e-4, max_iter=500)
+        ipm = opf.IPM(M, tol=1e-4, max_iter=500, chol_opts=copts)
         rc, it, obj = ipm.solve()
         torch.cuda.synchronize()
         return rc
@@ -112,7 +126,7 @@ def serving_bench(grids, slots, rate_factor):
         t_free = max(a, t_free) + sv
         lat_seq.append(t_free - a)
     def serve(at):
-        srv = opf.Server(slots=slots, hbm_budget=8 << 30)
+        srv = opf.Server(slots=slots, hbm_budget=8 << 30, chol_opts=copts)
         t0 = srv.now()
         for k, (tag, g) in enumerate(grids):
             while srv.now() - t0 < at[k]:
@@ -142,6 +156,7 @@ def serving_bench(grids, slots, rate_factor):
         "peak_pool_bytes": st["peak_in_use"],
         "sequential": {"solves_per_s": seq_rate, "p50_ms": 1e3 * pct(lat_seq, 50), "p99_ms": 1e3 * pct(lat_seq, 99),
                        "converged": conv_seq},
+        "autotune": tuning,
     }
 
 

@@ -10,11 +10,18 @@
 // instance parameters from structure-of-arrays buffers with coalesced loads,
 // gathers the bus voltages it needs, and writes its values into fixed,
 // family-major slots of c, J and H so that consecutive work-items write
-// consecutive addresses.  The derivatives are closed-form expressions of the
-// flow functions, written out below.
+// consecutive addresses.  Each template's nonlinear part is written once, as a
+// function of a generic number type (arc_flows, thermal, shunt, cost below):
+// instantiated with double it gives the constraint values, instantiated with
+// the second-order forward-mode Jet of jet.h it gives the value, the gradient
+// (Jacobian entries) and the Hessian over the instance's local inputs in one
+// evaluation (Section III-B).  Only the linear parts (the +-1 Jacobian entries
+// of the flow variables, arcs and generators in the balances, and the angle
+// differences) are written directly.
 #include <cmath>
 #include <cstdarg>
 
+#include "jet.h"
 #include "model.h"
 
 namespace opf {
@@ -55,6 +62,40 @@ struct AdParams {
 
 constexpr int AD_BLOCK = 256;
 
+// ---------------------------------------------------------------- template value expressions
+// Flow functions of arc i -> j (patterns 3-6) over its local inputs (va_i, va_j, vm_i, vm_j): series
+// admittance g + jb, half the line charging bc at each end, tap 1, no shift:
+//   phi_p = g vm_i^2 - vm_i vm_j (g cos(va_i - va_j) + b sin(va_i - va_j))
+//   phi_q = -(b + bc) vm_i^2 - vm_i vm_j (g sin(va_i - va_j) - b cos(va_i - va_j))
+template <class T>
+__device__ __forceinline__ void arc_flows(const T& vai, const T& vaj, const T& vi, const T& vj, double g, double b,
+                                          double bc, T* phip, T* phiq) {
+    T s, c;
+    sincos(vai - vaj, &s, &c);
+    const T vv = vi * vj;
+    const T vi2 = vi * vi;
+    *phip = g * vi2 - vv * (g * c + b * s);
+    *phiq = -(b + bc) * vi2 - vv * (g * s - b * c);
+}
+
+// thermal limit of an arc (patterns 8-9) over (p_a, q_a)
+template <class T>
+__device__ __forceinline__ T thermal(const T& p, const T& q) {
+    return p * p + q * q;
+}
+
+// shunt term of a bus balance (patterns 10-11) over vm: coef vm^2 (coef = Gs active, -Bs reactive)
+template <class T>
+__device__ __forceinline__ T shunt(const T& vm, double coef) {
+    return coef * (vm * vm);
+}
+
+// generator cost (pattern 1) over pg, without the constant c0 (which the objective adds)
+template <class T>
+__device__ __forceinline__ T cost(const T& pg, double c2, double c1) {
+    return c2 * (pg * pg) + c1 * pg;
+}
+
 __device__ __forceinline__ double rs(const double* cscale, int64_t row) { return cscale ? cscale[row] : 1.0; }
 
 __global__ __launch_bounds__(AD_BLOCK) void ad_templates(AdParams P) {
@@ -76,72 +117,66 @@ __global__ __launch_bounds__(AD_BLOCK) void ad_templates(AdParams P) {
         const double vai = P.x[ova + i], vaj = P.x[ova + j];
         const double vi = P.x[ovm + i], vj = P.x[ovm + j];
         const double pa = P.x[op + a], qa = P.x[oq + a];
-        const double th = vai - vaj;
-        double sn, cs;
-        sincos(th, &sn, &cs);
-        const double Cc = g * cs + bb * sn;  // d S / d th
-        const double S = g * sn - bb * cs;   // d Cc / d th = -S
-        const double vv = vi * vj;
         const int64_t rp = R.p + a, rq = R.q + a, rt = R.th + a;
         const double sp = rs(P.cscale, rp), sq = rs(P.cscale, rq), st = rs(P.cscale, rt);
-        if (wc) {
-            const double phip = g * vi * vi - vv * Cc;
-            const double phiq = -(bb + bc) * vi * vi - vv * S;
+        if (wc && !(wj || wh)) {
+            double phip, phiq;
+            arc_flows(vai, vaj, vi, vj, g, bb, bc, &phip, &phiq);
             P.c[rp] = sp * (pa - phip);
             P.c[rq] = sq * (qa - phiq);
-            P.c[rt] = st * (pa * pa + qa * qa);
-            if (a < E) P.c[R.ang + a] = rs(P.cscale, R.ang + a) * th;
+            P.c[rt] = st * thermal(pa, qa);
+            if (a < E) P.c[R.ang + a] = rs(P.cscale, R.ang + a) * (vai - vaj);
         }
-        if (wj) {
-            double* J = P.jac + JL.flow;
-            J[0 * (int64_t)A + a] = sp;
-            J[1 * (int64_t)A + a] = sp * (-vv * S);
-            J[2 * (int64_t)A + a] = sp * (vv * S);
-            J[3 * (int64_t)A + a] = sp * (-2.0 * g * vi + vj * Cc);
-            J[4 * (int64_t)A + a] = sp * (vi * Cc);
-            J[5 * (int64_t)A + a] = sq;
-            J[6 * (int64_t)A + a] = sq * (vv * Cc);
-            J[7 * (int64_t)A + a] = sq * (-vv * Cc);
-            J[8 * (int64_t)A + a] = sq * (2.0 * (bb + bc) * vi + vj * S);
-            J[9 * (int64_t)A + a] = sq * (vi * S);
-            P.jac[JL.th + a] = st * (2.0 * pa);
-            P.jac[JL.th + A + a] = st * (2.0 * qa);
-            if (a < E) {
-                const double sa = rs(P.cscale, R.ang + a);
-                P.jac[JL.ang + a] = sa;
-                P.jac[JL.ang + E + a] = -sa;
+        if (wj || wh) {
+            // local inputs 0..3 = (va_i, va_j, vm_i, vm_j); c_p = p_a - phi_p, c_q = q_a - phi_q
+            using J4 = Jet<4>;
+            J4 phip, phiq;
+            arc_flows(J4::input(vai, 0), J4::input(vaj, 1), J4::input(vi, 2), J4::input(vj, 3), g, bb, bc, &phip,
+                      &phiq);
+            using J2 = Jet<2>;
+            const J2 th2 = thermal(J2::input(pa, 0), J2::input(qa, 1));
+            if (wc) {
+                P.c[rp] = sp * (pa - phip.v);
+                P.c[rq] = sq * (qa - phiq.v);
+                P.c[rt] = st * th2.v;
+                if (a < E) P.c[R.ang + a] = rs(P.cscale, R.ang + a) * (vai - vaj);
             }
-            P.jac[JL.bal_parc + a] = rs(P.cscale, R.pb + i);
-            P.jac[JL.bal_qarc + a] = rs(P.cscale, R.qb + i);
-        }
-        if (wh) {
-            const double yp = P.y[rp] * sp, yq = P.y[rq] * sq, yt = P.y[rt] * st;
-            double* H = P.hess + HL.pflow;
-            // + y grad^2 phi_p over (va_i, va_j, vm_i, vm_j)
-            H[0 * (int64_t)A + a] = yp * (vv * Cc);
-            H[1 * (int64_t)A + a] = yp * (vv * Cc);
-            H[2 * (int64_t)A + a] = yp * (2.0 * g);
-            H[3 * (int64_t)A + a] = 0.0;
-            H[4 * (int64_t)A + a] = yp * (-vv * Cc);
-            H[5 * (int64_t)A + a] = yp * (vj * S);
-            H[6 * (int64_t)A + a] = yp * (vi * S);
-            H[7 * (int64_t)A + a] = yp * (-vj * S);
-            H[8 * (int64_t)A + a] = yp * (-vi * S);
-            H[9 * (int64_t)A + a] = yp * (-Cc);
-            // + y grad^2 phi_q
-            H = P.hess + HL.qflow;
-            H[0 * (int64_t)A + a] = yq * (vv * S);
-            H[1 * (int64_t)A + a] = yq * (vv * S);
-            H[2 * (int64_t)A + a] = yq * (-2.0 * (bb + bc));
-            H[3 * (int64_t)A + a] = 0.0;
-            H[4 * (int64_t)A + a] = yq * (-vv * S);
-            H[5 * (int64_t)A + a] = yq * (-vj * Cc);
-            H[6 * (int64_t)A + a] = yq * (-vi * Cc);
-            H[7 * (int64_t)A + a] = yq * (vj * Cc);
-            H[8 * (int64_t)A + a] = yq * (vi * Cc);
-            H[9 * (int64_t)A + a] = yq * (-S);
-            P.hess[HL.th + a] = -2.0 * yt;
-            P.hess[HL.th + A + a] = -2.0 * yt;
+            if (wj) {
+                double* J = P.jac + JL.flow;
+                J[0 * (int64_t)A + a] = sp;
+                J[5 * (int64_t)A + a] = sq;
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    J[(1 + k) * (int64_t)A + a] = -sp * phip.g[k];
+                    J[(6 + k) * (int64_t)A + a] = -sq * phiq.g[k];
+                }
+                P.jac[JL.th + a] = st * th2.g[0];
+                P.jac[JL.th + A + a] = st * th2.g[1];
+                if (a < E) {
+                    const double sa = rs(P.cscale, R.ang + a);
+                    P.jac[JL.ang + a] = sa;
+                    P.jac[JL.ang + E + a] = -sa;
+                }
+                P.jac[JL.bal_parc + a] = rs(P.cscale, R.pb + i);
+                P.jac[JL.bal_qarc + a] = rs(P.cscale, R.qb + i);
+            }
+            if (wh) {
+                // the Lagrangian's -y grad^2 c = +y grad^2 phi over the ten lower entries of (va_i, va_j, vm_i,
+                // vm_j), in the Hessian layout's order
+                constexpr int slot_i[10] = {0, 1, 2, 3, 1, 2, 3, 2, 3, 3};
+                constexpr int slot_j[10] = {0, 1, 2, 3, 0, 0, 0, 1, 1, 2};
+                const double yp = P.y[rp] * sp, yq = P.y[rq] * sq, yt = P.y[rt] * st;
+                double* Hp = P.hess + HL.pflow;
+                double* Hq = P.hess + HL.qflow;
+#pragma unroll
+                for (int k = 0; k < 10; k++) {
+                    const int q = J4::hi(slot_i[k], slot_j[k]);
+                    Hp[k * (int64_t)A + a] = yp * phip.h[q];
+                    Hq[k * (int64_t)A + a] = yq * phiq.h[q];
+                }
+                P.hess[HL.th + a] = -yt * th2.h[J2::hi(0, 0)];
+                P.hess[HL.th + A + a] = -yt * th2.h[J2::hi(1, 1)];
+            }
         }
         return;
     }
@@ -167,18 +202,21 @@ __global__ __launch_bounds__(AD_BLOCK) void ad_templates(AdParams P) {
                 gp += P.x[opg + gk];
                 gq += P.x[oqg + gk];
             }
-            P.c[rpb] = spb * (sp - gp + P.pd[i] + gsi * vm * vm);
-            P.c[rqb] = sqb * (sq - gq + P.qd[i] - bsi * vm * vm);
+            P.c[rpb] = spb * (sp - gp + P.pd[i] + shunt(vm, gsi));
+            P.c[rqb] = sqb * (sq - gq + P.qd[i] + shunt(vm, -bsi));
             if (i == P.ref) P.c[R.ref] = rs(P.cscale, R.ref) * P.x[ova + i];
         }
-        if (wj) {
-            P.jac[JL.bal_pvm + i] = spb * (2.0 * gsi * vm);
-            P.jac[JL.bal_qvm + i] = sqb * (-2.0 * bsi * vm);
-            if (i == P.ref) P.jac[JL.ref] = rs(P.cscale, R.ref);
-        }
-        if (wh) {
-            P.hess[HL.bal_p + i] = (P.y[rpb] * spb) * (-2.0 * gsi);
-            P.hess[HL.bal_q + i] = (P.y[rqb] * sqb) * (2.0 * bsi);
+        if (wj || wh) {
+            const Jet<1> shp = shunt(Jet<1>::input(vm, 0), gsi), shq = shunt(Jet<1>::input(vm, 0), -bsi);
+            if (wj) {
+                P.jac[JL.bal_pvm + i] = spb * shp.g[0];
+                P.jac[JL.bal_qvm + i] = sqb * shq.g[0];
+                if (i == P.ref) P.jac[JL.ref] = rs(P.cscale, R.ref);
+            }
+            if (wh) {
+                P.hess[HL.bal_p + i] = -(P.y[rpb] * spb) * shp.h[0];
+                P.hess[HL.bal_q + i] = -(P.y[rqb] * sqb) * shq.h[0];
+            }
         }
         return;
     }
@@ -188,13 +226,14 @@ __global__ __launch_bounds__(AD_BLOCK) void ad_templates(AdParams P) {
         int k = b * AD_BLOCK + threadIdx.x;
         if (k >= G) return;
         const double pg = P.x[opg + k];
-        if (wg) P.grad[opg + k] = P.gscale * (2.0 * P.c2[k] * pg + P.c1[k]);
+        const Jet<1> f = cost(Jet<1>::input(pg, 0), P.c2[k], P.c1[k]);
+        if (wg) P.grad[opg + k] = P.gscale * f.g[0];
         if (wj) {
             const int i = P.gbus[k];
             P.jac[JL.bal_pg + k] = -rs(P.cscale, R.pb + i);
             P.jac[JL.bal_qg + k] = -rs(P.cscale, R.qb + i);
         }
-        if (wh) P.hess[HL.gen + k] = P.obj_weight * (2.0 * P.c2[k]);
+        if (wh) P.hess[HL.gen + k] = P.obj_weight * f.h[0];
         return;
     }
     b -= P.gen_blocks;
@@ -215,7 +254,7 @@ __global__ __launch_bounds__(256) void ad_objective(int N, int G, const double* 
     double acc = 0.0;
     for (int k = threadIdx.x; k < G; k += 256) {
         double pg = x[2 * N + k];
-        acc += c2[k] * pg * pg + c1[k] * pg + c0[k];
+        acc += cost(pg, c2[k], c1[k]) + c0[k];
     }
     sh[threadIdx.x] = acc;
     __syncthreads();
