@@ -160,6 +160,65 @@ def serving_bench(grids, slots, rate_factor):
     }
 
 
+def stage_probe(grid, reps=20, warm=5, flush_mib=1024):
+    """The AD (every template: constraints, gradient, the x-dependent Jacobian entries and the Hessian, as the
+    IPM evaluates them) and condensed-assembly kernels alone on one grid, each timed with HIP events cold (after
+    writing a buffer larger than the last-level cache) and warm (back to back), median and p90 over `reps`
+    runs after `warm` untimed ones, and their algorithmic HBM rates (values only, index maps excluded)."""
+    import torch
+    from paper_2307_16830_amd import opf
+    M = opf.Model(grid)
+    n, m = M.n, M.m
+    dev = "cuda"
+    x = torch.tensor(M.initial_point(), dtype=torch.float64, device=dev)
+    y = torch.linspace(-1.0, 1.0, m, dtype=torch.float64, device=dev)
+    f = torch.empty(1, dtype=torch.float64, device=dev)
+    c = torch.empty(m, dtype=torch.float64, device=dev)
+    g = torch.empty(n, dtype=torch.float64, device=dev)
+    jac = torch.empty(M.nnzj, dtype=torch.float64, device=dev)
+    hess = torch.empty(M.nnzh, dtype=torch.float64, device=dev)
+    sigx = torch.ones(n, dtype=torch.float64, device=dev)
+    dvec = torch.full((m,), 100.0, dtype=torch.float64, device=dev)
+    kval = torch.empty(M.nnzk, dtype=torch.float64, device=dev)
+    flush = torch.empty(flush_mib << 17, dtype=torch.float64, device=dev)
+    what = opf.EVAL_C | opf.EVAL_GRAD | opf.EVAL_JAC | opf.EVAL_HESS
+    M.eval_derivs(what, x, y, 1.0, c=c, grad=g, jac=jac, hess=hess)  # writes the constant Jacobian entries once
+    ad = lambda: M.eval_derivs(what | opf.EVAL_JAC_VAR, x, y, 1.0, c=c, grad=g, jac=jac, hess=hess)
+    asm = lambda: M.condense(hess, jac, sigx, dvec, 0.0, kval)
+    ad()
+    asm()
+    N, E, G = grid.nbus, grid.nbranch, grid.ngen
+    nconst = 10 * E + 2 * G + 1
+    # AD: x and y in, template parameters in (per branch g, b, b/2 and two bus indices;
+    # per bus pd, qd, gs, bs; per generator c2, c1 and its bus), c, gradient, the x-dependent Jacobian entries
+    # and the Hessian out
+    ad_bytes = 8.0 * (n + m) + 32.0 * E + 32.0 * N + 20.0 * G + 8.0 * (m + n + (M.nnzj - nconst) + M.nnzh)
+    asm_bytes = 8.0 * (M.nnzh + M.nnzj + m + n + M.nnzk)
+    out = {}
+    for name, fn, nbytes in (("ad", ad, ad_bytes), ("assembly", asm, asm_bytes)):
+        res = {}
+        for mode in ("cold", "warm"):
+            ts = []
+            for _ in range(warm):
+                fn()
+            for _ in range(reps):
+                if mode == "cold":
+                    flush.fill_(1.0)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                fn()
+                e1.record()
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            ms = float(np.median(ts))
+            res[mode] = {"ms": ms, "p90_ms": pct(ts, 90), "gbs": nbytes / (ms * 1e-3) / 1e9,
+                         "frac_hbm": nbytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
+        res["algorithmic_bytes"] = nbytes
+        out[name] = res
+    del flush
+    return out
+
+
 def cpu_baseline(grid, budget_s):
     """The oracle (plain CPU reference) timed on one IPM iteration of the same grid, analysis excluded."""
     from oracle import ipm as oipm
@@ -185,6 +244,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graphs", action="store_true", help="plain kernel launches instead of graph replay")
+    ap.add_argument("--stage-probe", default=None, metavar="CONFIG",
+                    help="also time the AD and assembly kernels alone, cold and warm, on this configuration")
     ap.add_argument("--serving", type=int, default=512, metavar="REQUESTS",
                     help="also run this many requests of the serving trace through the batched server and one at "
                          "a time (0: skip)")
@@ -293,7 +354,10 @@ def main():
     # and outputs; template parameters and index maps excluded): Hessian (x, y in; H out), the new point (x in;
     # c, J, gradient out) and every line-search trial (x in; c out)
     trials = float(np.mean([i["ls_trials"] for i in timed]))
-    ad_bytes = 8.0 * (M.n + M.m + M.nnzh) + 8.0 * (M.n + M.m + M.nnzj + M.n) + trials * 8.0 * (M.n + M.m)
+    # (the point evaluation rewrites only the x-dependent Jacobian entries: 10 E + 2 G + 1 are constant)
+    nconst = 10 * E + 2 * G + 1
+    ad_bytes = (8.0 * (M.n + M.m + M.nnzh) + 8.0 * (M.n + M.m + M.nnzj - nconst + M.n)
+                + trials * 8.0 * (M.n + M.m))
     asm_bytes = 8.0 * (M.nnzh + M.nnzj + M.m + M.n + M.nnzk)
     out = {
         "metric": "ACOPF IPM iter/s at 10k buses",
@@ -332,6 +396,11 @@ def main():
         log(f"[bench] serving: {len(sgrids)} requests, {args.serving_slots} slots")
         out["serving"] = serving_bench(sgrids, args.serving_slots, args.serving_rate)
         log(f"[bench] serving: {out['serving']}")
+    if args.stage_probe:
+        log(f"[bench] stage probe on {args.stage_probe}")
+        out["stage_probe"] = {"config": args.stage_probe,
+                              **stage_probe(gridgen.make_config(args.stage_probe))}
+        log(f"[bench] stage probe: {out['stage_probe']}")
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on one iteration of the same grid")
         out["cpu_baseline"] = cpu_baseline(grid, 30.0)

@@ -115,8 +115,14 @@ int opf_initial_point(const opf_model* model, double* x0);
  *   f [1]   objective value,            c [m] constraint values,
  *   grad [n] objective gradient,        jac [nnz_jac] Jacobian values,
  *   hess [nnz_hess] values of obj_weight * grad^2 f - sum_i y_i grad^2 c_i
- * (the Lagrangian L = f - y^T g of Section II-A).  Asynchronous on stream. */
-enum { OPF_EVAL_F = 1, OPF_EVAL_C = 2, OPF_EVAL_GRAD = 4, OPF_EVAL_JAC = 8, OPF_EVAL_HESS = 16 };
+ * (the Lagrangian L = f - y^T g of Section II-A).  Asynchronous on stream.
+ * OPF_EVAL_JAC_VAR (only together with OPF_EVAL_JAC) writes just the Jacobian
+ * entries that depend on x and leaves the constant ones (the unit coefficients
+ * of the flow variables, the angle-difference rows, the generator and arc
+ * columns of the balance rows, the reference row) as an earlier OPF_EVAL_JAC
+ * call without it wrote them into the same buffer. */
+enum { OPF_EVAL_F = 1, OPF_EVAL_C = 2, OPF_EVAL_GRAD = 4, OPF_EVAL_JAC = 8, OPF_EVAL_HESS = 16,
+       OPF_EVAL_JAC_VAR = 32 };
 int opf_eval_derivs(opf_model* model, unsigned what, const double* x, const double* y, double obj_weight,
                     double* f, double* c, double* grad, double* jac, double* hess, void* stream);
 

@@ -413,6 +413,7 @@ __global__ void k_update(int n, int m, double alpha, double az, double mu, doubl
 // ------------------------------------------------------------------------ state
 struct ipm_state {
     opf_model* M = nullptr;
+    bool jac_const = false;  // the scaled Jacobian's constant entries are in jac
     chol_sym* C = nullptr;
     ipm_options o{};
     Consts K;
@@ -501,8 +502,10 @@ double read_scalar(ipm_state* S, const double* dptr) {
 
 void eval_point(ipm_state* S, hipEvent_t after_eval) {
     // scaled gradient, constraints and Jacobian at x, plus J^T y
-    eval_derivs(S->M, OPF_EVAL_F | OPF_EVAL_C | OPF_EVAL_GRAD | OPF_EVAL_JAC, S->x.p, S->y.p, S->sf, S->sc.p,
-                S->sf, S->f.p, S->c.p, S->g.p, S->jac.p, nullptr, S->st);
+    // the Jacobian's constant entries (fixed by the row scaling) are written by the first evaluation only
+    eval_derivs(S->M, OPF_EVAL_F | OPF_EVAL_C | OPF_EVAL_GRAD | OPF_EVAL_JAC | (S->jac_const ? OPF_EVAL_JAC_VAR : 0),
+                S->x.p, S->y.p, S->sf, S->sc.p, S->sf, S->f.p, S->c.p, S->g.p, S->jac.p, nullptr, S->st);
+    S->jac_const = true;
     if (after_eval) OPF_HIP(hipEventRecord(after_eval, S->st));
     jt_times(S->M, S->jac.p, S->y.p, nullptr, S->jty.p, S->st);
 }

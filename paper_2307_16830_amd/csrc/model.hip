@@ -107,6 +107,7 @@ __global__ __launch_bounds__(AD_BLOCK) void ad_templates(AdParams P) {
     const int ova = 0, ovm = N, opg = 2 * N, oqg = 2 * N + G, op = 2 * N + 2 * G, oq = op + A;
     const bool wc = P.what & OPF_EVAL_C, wj = P.what & OPF_EVAL_JAC, wh = P.what & OPF_EVAL_HESS,
                wg = P.what & OPF_EVAL_GRAD;
+    const bool wjc = wj && !(P.what & OPF_EVAL_JAC_VAR);  // constant Jacobian entries too
     int b = blockIdx.x;
     if (b < P.arc_blocks) {
         // ---------------- arc template: patterns 3-6 (flows), 8-9 (thermal), 7 (angle on a < E)
@@ -143,8 +144,6 @@ __global__ __launch_bounds__(AD_BLOCK) void ad_templates(AdParams P) {
             }
             if (wj) {
                 double* J = P.jac + JL.flow;
-                J[0 * (int64_t)A + a] = sp;
-                J[5 * (int64_t)A + a] = sq;
 #pragma unroll
                 for (int k = 0; k < 4; k++) {
                     J[(1 + k) * (int64_t)A + a] = -sp * phip.g[k];
@@ -152,13 +151,17 @@ __global__ __launch_bounds__(AD_BLOCK) void ad_templates(AdParams P) {
                 }
                 P.jac[JL.th + a] = st * th2.g[0];
                 P.jac[JL.th + A + a] = st * th2.g[1];
-                if (a < E) {
-                    const double sa = rs(P.cscale, R.ang + a);
-                    P.jac[JL.ang + a] = sa;
-                    P.jac[JL.ang + E + a] = -sa;
+                if (wjc) {
+                    J[0 * (int64_t)A + a] = sp;
+                    J[5 * (int64_t)A + a] = sq;
+                    if (a < E) {
+                        const double sa = rs(P.cscale, R.ang + a);
+                        P.jac[JL.ang + a] = sa;
+                        P.jac[JL.ang + E + a] = -sa;
+                    }
+                    P.jac[JL.bal_parc + a] = rs(P.cscale, R.pb + i);
+                    P.jac[JL.bal_qarc + a] = rs(P.cscale, R.qb + i);
                 }
-                P.jac[JL.bal_parc + a] = rs(P.cscale, R.pb + i);
-                P.jac[JL.bal_qarc + a] = rs(P.cscale, R.qb + i);
             }
             if (wh) {
                 // the Lagrangian's -y grad^2 c = +y grad^2 phi over the ten lower entries of (va_i, va_j, vm_i,
@@ -211,7 +214,7 @@ __global__ __launch_bounds__(AD_BLOCK) void ad_templates(AdParams P) {
             if (wj) {
                 P.jac[JL.bal_pvm + i] = spb * shp.g[0];
                 P.jac[JL.bal_qvm + i] = sqb * shq.g[0];
-                if (i == P.ref) P.jac[JL.ref] = rs(P.cscale, R.ref);
+                if (wjc && i == P.ref) P.jac[JL.ref] = rs(P.cscale, R.ref);
             }
             if (wh) {
                 P.hess[HL.bal_p + i] = -(P.y[rpb] * spb) * shp.h[0];
@@ -228,7 +231,7 @@ __global__ __launch_bounds__(AD_BLOCK) void ad_templates(AdParams P) {
         const double pg = P.x[opg + k];
         const Jet<1> f = cost(Jet<1>::input(pg, 0), P.c2[k], P.c1[k]);
         if (wg) P.grad[opg + k] = P.gscale * f.g[0];
-        if (wj) {
+        if (wjc) {
             const int i = P.gbus[k];
             P.jac[JL.bal_pg + k] = -rs(P.cscale, R.pb + i);
             P.jac[JL.bal_qg + k] = -rs(P.cscale, R.qb + i);
@@ -591,7 +594,9 @@ extern "C" int opf_eval_derivs(opf_model* M, unsigned what, const double* x, con
                                double* f, double* c, double* grad, double* jac, double* hess, void* stream) {
     return guarded([&] {
         OPF_CHECK(M && x, OPF_E_INVALID, "opf_eval_derivs: null model or x");
-        OPF_CHECK(!(what & ~31u), OPF_E_INVALID, "opf_eval_derivs: unknown flag bits");
+        OPF_CHECK(!(what & ~63u), OPF_E_INVALID, "opf_eval_derivs: unknown flag bits");
+        OPF_CHECK(!(what & OPF_EVAL_JAC_VAR) || (what & OPF_EVAL_JAC), OPF_E_INVALID,
+                  "opf_eval_derivs: OPF_EVAL_JAC_VAR needs OPF_EVAL_JAC");
         OPF_CHECK(!(what & OPF_EVAL_F) || f, OPF_E_INVALID, "opf_eval_derivs: f is NULL");
         OPF_CHECK(!(what & OPF_EVAL_C) || c, OPF_E_INVALID, "opf_eval_derivs: c is NULL");
         OPF_CHECK(!(what & OPF_EVAL_GRAD) || grad, OPF_E_INVALID, "opf_eval_derivs: grad is NULL");

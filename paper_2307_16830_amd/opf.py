@@ -23,7 +23,7 @@ VP = ctypes.c_void_p
 
 OK, E_INVALID, E_NOMEM, E_DEVICE, E_STATE, E_NOT_PD, E_MAXITER, E_LINESEARCH, E_NUMERIC, E_BUDGET = \
     0, -1, -2, -3, -4, -5, -6, -7, -8, -9
-EVAL_F, EVAL_C, EVAL_GRAD, EVAL_JAC, EVAL_HESS = 1, 2, 4, 8, 16
+EVAL_F, EVAL_C, EVAL_GRAD, EVAL_JAC, EVAL_HESS, EVAL_JAC_VAR = 1, 2, 4, 8, 16, 32
 EXPORTED = [
     "opf_last_error", "opf_default_options", "opf_create", "opf_destroy", "opf_dims", "opf_structure", "opf_bounds", "opf_initial_point",
     "opf_eval_derivs", "kkt_pattern", "kkt_condense", "chol_default_options", "chol_analyze", "chol_destroy",

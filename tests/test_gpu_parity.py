@@ -107,6 +107,44 @@ def test_derivatives_match_oracle(case):
     assert_close(a[2], b[2], b[3], "hessian")
 
 
+@pytest.mark.parametrize("case", ["cfg0", (12, 16, 3, 5)])
+def test_variable_only_jacobian_keeps_constant_entries(case):
+    """OPF_EVAL_JAC_VAR rewrites exactly the entries that depend on x: over a full evaluation at another
+    point it reproduces the full evaluation bit for bit, and into a NaN-filled buffer it leaves NaN in
+    exactly the 10E + 2G + 1 constant entries (unit flow coefficients, angle rows, generator and arc columns
+    of the balance rows, reference row), whose oracle values do not move with x."""
+    g = grid_for(case)
+    M = opf().Model(g)
+    om = OModel(g)
+    O = opf()
+    x1, _ = random_xy(om, 3)
+    x2, _ = random_xy(om, 4)
+    full = torch.zeros(M.nnzj, dtype=torch.float64, device="cuda")
+    M.eval_derivs(O.EVAL_JAC, dev(x1), jac=full)
+    buf = torch.zeros(M.nnzj, dtype=torch.float64, device="cuda")
+    M.eval_derivs(O.EVAL_JAC, dev(x2), jac=buf)
+    M.eval_derivs(O.EVAL_JAC | O.EVAL_JAC_VAR, dev(x1), jac=buf)
+    assert np.array_equal(host(buf).view(np.int64), host(full).view(np.int64))
+    nanbuf = torch.full((M.nnzj,), float("nan"), dtype=torch.float64, device="cuda")
+    M.eval_derivs(O.EVAL_JAC | O.EVAL_JAC_VAR, dev(x1), jac=nanbuf)
+    kept = np.isnan(host(nanbuf))
+    assert kept.sum() == 10 * g.nbranch + 2 * g.ngen + 1
+    jr, jc, _, _ = M.structure()
+    key = jr.astype(np.int64) * M.n + jc
+    assert not np.intersect1d(key[kept], key[~kept]).size  # no position mixes constant and variable terms
+    a1 = canonical(jr[kept], jc[kept], host(full)[kept], np.zeros(kept.sum()), shape=(M.m, M.n))
+    o1 = om.jacobian(x1)
+    o2 = om.jacobian(x2)
+    b1 = canonical(o1[0], o1[1], o1[2], o1[3], shape=(M.m, M.n))
+    b2 = canonical(o2[0], o2[1], o2[2], o2[3], shape=(M.m, M.n))
+    pos = {(r, c): k for k, (r, c) in enumerate(zip(b1[0], b1[1]))}
+    idx = np.array([pos[(r, c)] for r, c in zip(a1[0], a1[1])])
+    assert np.array_equal(b1[2][idx], b2[2][idx])
+    assert np.array_equal(a1[2], b1[2][idx])
+    with pytest.raises(O.OpfError):
+        M.eval_derivs(O.EVAL_JAC_VAR, dev(x1), jac=nanbuf)
+
+
 def _condensed_inputs(om, M, seed, dw):
     rng = np.random.default_rng(seed)
     x, y = random_xy(om, seed)
