@@ -143,8 +143,10 @@ def serving_bench(grids, slots, rate_factor):
         srv.close()
         return res, st, max(r["t_done"] for r in res.values()) - t0
 
+    g0 = opf.graph_stats()
     res_all, _, span_all = serve(np.zeros(len(grids)))  # every request at once: the server's capacity
     res, st, makespan = serve(arrive)
+    g1 = opf.graph_stats()
     lat = [r["t_done"] - r["t_submit"] for r in res.values()]
     return {
         "requests": len(grids), "slots": slots,
@@ -153,7 +155,10 @@ def serving_bench(grids, slots, rate_factor):
         "solves_per_s": len(grids) / makespan, "p50_ms": 1e3 * pct(lat, 50), "p99_ms": 1e3 * pct(lat, 99),
         "solves_per_s_all_at_once": len(grids) / span_all,
         "converged": sum(r["status"] == 1 for r in res.values()),
+        "not_converged": sorted({(opf.status_name(r["status"]), r["message"][:120]) for r in res.values()
+                                 if r["status"] != 1}),
         "peak_pool_bytes": st["peak_in_use"],
+        "graph_captures": g1[0] - g0[0], "graph_capture_fallbacks": g1[1] - g0[1],
         "sequential": {"solves_per_s": seq_rate, "p50_ms": 1e3 * pct(lat_seq, 50), "p99_ms": 1e3 * pct(lat_seq, 99),
                        "converged": conv_seq},
         "autotune": tuning,
@@ -244,6 +249,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graphs", action="store_true", help="plain kernel launches instead of graph replay")
+    ap.add_argument("--chol-options", default=None, metavar="JSON",
+                    help="factorization options for the IPM (chol_options fields, e.g. '{\"pair_min\": 1024}')")
     ap.add_argument("--stage-probe", default=None, metavar="CONFIG",
                     help="also time the AD and assembly kernels alone, cold and warm, on this configuration")
     ap.add_argument("--serving", type=int, default=512, metavar="REQUESTS",
@@ -284,7 +291,10 @@ def main():
     t0 = time.perf_counter()
     # at 80k buses exact minimum degree stops once the minimum degree reaches 1,500 (the rest, ~42.6k columns,
     # is ordered by index into one dense front); below that the relative dense-tail rule alone applies
-    copts = opf.chol_options(dense_abs=1500) if args.config == "cfg3" else None
+    ckw = dict(dense_abs=1500) if args.config == "cfg3" else {}
+    if args.chol_options:
+        ckw.update(json.loads(args.chol_options))
+    copts = opf.chol_options(**ckw) if ckw else None
     ipm = opf.IPM(M, tol=args.tol, max_iter=10000, chol_opts=copts, stream=stream.cuda_stream,
                   graphs=0 if args.no_graphs else 1)
     torch.cuda.synchronize()
@@ -381,6 +391,7 @@ def main():
                       "note": "algorithmic bytes (values only) over stage time from HIP events per iteration; "
                               "AD = Hessian + constraint/Jacobian/gradient evaluations of the iteration"},
         "analysis_s": t_analyze,
+        "chol_options": ckw or "defaults",
         "roofline": {"bound": "mfma", "achieved": achieved_tflops, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tflops / PEAK_FP64_TFLOPS, "traffic": recorded_traffic(args.config, kname),
                      "kernel": kname, "avg_launch_ms": avg_ms, "launches": kt["launches"],

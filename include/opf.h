@@ -200,6 +200,12 @@ int chol_supernode_rows(const chol_sym* sym, int64_t* rows_ptr, int32_t* rows);
  * elimination level), else OPF_OK and *bad_col = -1.  The factor stays in
  * HBM. */
 int chol_factor(chol_sym* sym, const double* kval, void* stream, int32_t* bad_col);
+/* Diagnostics (process-wide, since load): how many factorization and solve
+ * launch sequences were captured into HIP graphs (handles an IPM owns, on a
+ * stream of its own), and how many of those captures failed and were
+ * enqueued as plain launches instead (e.g. when another thread's work on the
+ * legacy null stream invalidated them).  Host outputs. */
+int chol_graph_stats(int64_t* captures, int64_t* fallbacks);
 /* x = K^{-1} b using the last successful factor; b, x device [n*nrhs]
  * (column-major, leading dimension n; x may alias b).  Returns after the
  * solve has run on `stream`: fronts with many pivots are solved by
@@ -376,6 +382,7 @@ typedef struct {
     int32_t n, m;         /* variables and rows of the request's model */
     int64_t footprint;    /* device bytes the request held while admitted */
     double t_submit, t_admit, t_done;  /* host steady-clock seconds (same clock as opf_serve_now) */
+    char message[160];    /* status < 0: the library's message for the failure (NUL-terminated), else "" */
 } serve_result;
 
 typedef struct opf_server opf_server;

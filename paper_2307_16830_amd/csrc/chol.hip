@@ -24,6 +24,7 @@
 // result for the parent) and then downward (each front gathers the already
 // computed solution at its off-diagonal rows).
 #include <algorithm>
+#include <atomic>
 #include <climits>
 #include <cmath>
 #include <mutex>
@@ -83,6 +84,12 @@ struct chol_sym {
     DBuf<int32_t> next_slot;  // per trailing-update item: slot of the next panel's diagonal block, or -1
 
     DBuf<int32_t> status;
+    DBuf<int32_t> level_d;    // elimination level of each supernode
+    DBuf<int64_t> statwords;  // [0]: first rejected pivot as (level << 32 | pivot), INT64_MAX if none
+    // host words the factorization status and the fault words are read into: pinned memory lent by the
+    // owning IPM (chol_bind_host), else allocated at the first factorization
+    int64_t* hwords = nullptr;
+    bool own_hwords = false;
     DBuf<double> fronts, upd, work, ybuf;
     DBuf<double> ldiag, rdiag;  // compact diagonal blocks and reciprocal pivots of one blocked step
     // sync-free solves of wide fronts
@@ -123,6 +130,7 @@ struct chol_sym {
     ~chol_sym() {
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
         for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
+        if (own_hwords && hwords) (void)hipHostFree(hwords);
     }
 };
 
@@ -256,16 +264,20 @@ __device__ __forceinline__ double lane_value(double v, int l) {
 // Cholesky of the kb x kb diagonal block at (k0, k0) of front s by the NW = 4 waves of a work-group,
 // pipelined over the waves.  Lane i holds row i; wave w owns the 16 columns [16w, 16w + 16) in
 // registers.  A wave first applies every earlier column of L (produced by the waves before it) to its
-// own columns as soon as that column appears in LDS, then factors its own 16 pivots: pivot k is read
-// from lane k, scaled by a Newton-refined reciprocal square root, the finished column is published to
-// LDS, and the wave's later columns are updated with the column's entries read lane by lane.  A column
-// "appears" when its LDS slots no longer hold a sentinel NaN bit pattern that no computed value takes,
-// so there is no separate flag or fence.  A partial block is padded with the identity.  Besides writing
-// L_D into the front, the block is left in ldiag slot `slot` (64 x 64 column-major, identity padding)
-// with the reciprocal pivots in rdiag (ones past kb) for the panel solve, and status[s] is lowered to the
-// first rejected pivot (pivot <= tol |K_jj|, replaced by 1).  All NT threads must call it; `colbuf` is
-// 64 x 64 doubles of LDS (16-byte aligned) and `badmin` an int of LDS.
+// own columns as soon as that column is in LDS, then factors its own 16 pivots: pivot k is read from
+// lane k and scaled by a Newton-refined reciprocal square root, and the finished column is written to
+// LDS.  Only the next column's update sits on the pivot-to-pivot path (two lane reads); the wave's
+// other columns are updated from broadcast LDS reads of the column just written.  Finished columns are
+// announced by a counter in LDS, raised after the column writes have completed (every second column and
+// at the end of the wave's block), so a consumer reads the counter only when it has caught up.  The
+// pivot loop is instantiated per wave so that the lanes it reads are immediates.  A partial block is
+// padded with the identity.  Besides writing L_D into the front, the block is left in ldiag slot `slot`
+// (64 x 64 column-major, identity padding) with the reciprocal pivots in rdiag (ones past kb) for the
+// panel solve, and status[s] is lowered to the first rejected pivot (pivot <= tol |K_jj|, replaced by
+// 1).  All NT threads must call it; `colbuf` is 64 x 64 doubles of LDS (16-byte aligned) and `flags`
+// two ints of LDS.
 constexpr int PW = 16;  // columns per wave in the pipelined diagonal-block Cholesky
+constexpr int PUB = 2;  // columns per raise of the column counter
 
 __device__ __forceinline__ double rsqrt_refined(double d) {
     double y = __builtin_amdgcn_rsq(d);  // hardware estimate, then two Newton steps for 1/sqrt(d)
@@ -281,70 +293,17 @@ __device__ __forceinline__ bool is_sentinel(double v) {
     return (unsigned long long)__double_as_longlong(v) == SENTINEL_BITS;
 }
 
-__device__ __forceinline__ void potrf_block(int s, int k0, int slot, const int32_t* __restrict__ first,
-                                            const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
-                                            const int64_t* __restrict__ foff, double* __restrict__ fronts,
-                                            double* __restrict__ ldiag, double* __restrict__ rdiag,
-                                            int32_t* __restrict__ status, const PivotRef& pr, double* colbuf,
-                                            int* badmin) {
+// The 16 pivots of wave W (its columns in a[], every earlier column already applied).  thr: lane k holds
+// pivot k's acceptance threshold.  Returns the first rejected pivot of the block (INT_MAX: none).
+template <int W>
+__device__ __forceinline__ int potrf_own(double (&a)[PW], double thr, double* colbuf, int* ready,
+                                         double& myrinv) {
     const int lane = threadIdx.x % 64;
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
-    const int m = mrows[s];
-    const int kb = min(TB, ncol[s] - k0);
-    double* F = fronts + foff[s] + (int64_t)k0 + (int64_t)m * k0;
-    const int p0 = first[s] + k0;
-    const double sentinel = __longlong_as_double((long long)SENTINEL_BITS);
-    for (int e = threadIdx.x; e < TB * TB; e += NT) colbuf[e] = sentinel;
-    if (threadIdx.x == 0) *badmin = INT_MAX;
-    const double thr = lane < kb ? pr.thresh(p0 + lane) : 0.0;  // lane k holds pivot k's threshold
-    double a[PW];
-#pragma unroll
-    for (int c = 0; c < PW; c++) {
-        const int j = PW * w + c;
-        a[c] = (j < kb && lane < kb) ? (j <= lane ? F[lane + (int64_t)m * j] : 0.0) : (j == lane ? 1.0 : 0.0);
-    }
-    __syncthreads();
-    // columns of the waves before this one, two at a time
-    for (int k = 0; k < PW * w; k += 2) {
-        double l0, l1;
-        double2 u0[PW / 2], u1[PW / 2];
-        int spins = 0;
-        bool wait;
-        do {
-            asm volatile("" ::: "memory");
-            l0 = colbuf[TB * k + lane];
-            l1 = colbuf[TB * (k + 1) + lane];
-#pragma unroll
-            for (int q = 0; q < PW / 2; q++) {
-                u0[q] = *reinterpret_cast<const double2*>(&colbuf[TB * k + PW * w + 2 * q]);
-                u1[q] = *reinterpret_cast<const double2*>(&colbuf[TB * (k + 1) + PW * w + 2 * q]);
-            }
-            bool pending = is_sentinel(l0) || is_sentinel(l1);
-#pragma unroll
-            for (int q = 0; q < PW / 2; q++)
-                pending = pending || is_sentinel(u0[q].x) || is_sentinel(u0[q].y) || is_sentinel(u1[q].x) ||
-                          is_sentinel(u1[q].y);
-            // bounded: the producing waves belong to this work-group and always progress
-            wait = __any(pending) && ++spins < (1 << 22);
-        } while (wait);
-#pragma unroll
-        for (int q = 0; q < PW / 2; q++) {
-            a[2 * q] = fma(-l0, u0[q].x, a[2 * q]);
-            a[2 * q + 1] = fma(-l0, u0[q].y, a[2 * q + 1]);
-        }
-#pragma unroll
-        for (int q = 0; q < PW / 2; q++) {
-            a[2 * q] = fma(-l1, u1[q].x, a[2 * q]);
-            a[2 * q + 1] = fma(-l1, u1[q].y, a[2 * q + 1]);
-        }
-    }
-    // own pivots
     int bad = INT_MAX;
-    double myrinv = 1.0;
+    double d = lane_value(a[0], PW * W);
 #pragma unroll
     for (int c = 0; c < PW; c++) {
-        const int k = PW * w + c;
-        double d = lane_value(a[c], k);
+        const int k = PW * W + c;
         if (!(d > lane_value(thr, k))) {
             bad = min(bad, k);
             d = 1.0;
@@ -354,9 +313,86 @@ __device__ __forceinline__ void potrf_block(int s, int k0, int slot, const int32
         if (lane == k) myrinv = rinv;
         a[c] = lik;
         colbuf[TB * k + lane] = lik;
-        asm volatile("" ::: "memory");  // publish now, not after the wave's later pivots
+        if (c + 1 < PW) {
+            a[c + 1] = fma(-lik, lane_value(lik, k + 1), a[c + 1]);
+            d = lane_value(a[c + 1], k + 1);
+        }
+        // entries (16 W + c2, k) for c2 > c + 1, read back as broadcasts in aligned pairs (LDS keeps a wave's
+        // accesses in order, so the reads see the write above)
 #pragma unroll
-        for (int c2 = c + 1; c2 < PW; c2++) a[c2] = fma(-lik, lane_value(lik, PW * w + c2), a[c2]);
+        for (int q = (c + 2) / 2; q < PW / 2; q++) {
+            const double2 u = *reinterpret_cast<const double2*>(&colbuf[TB * k + PW * W + 2 * q]);
+            if (2 * q >= c + 2) a[2 * q] = fma(-lik, u.x, a[2 * q]);
+            a[2 * q + 1] = fma(-lik, u.y, a[2 * q + 1]);
+        }
+        if (c % PUB == PUB - 1 || c == PW - 1) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");  // the column writes have completed
+            if (lane == 0) __hip_atomic_store(ready, k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+    }
+    return bad;
+}
+
+// Lane k's acceptance threshold for pivot k of the diagonal block at (k0, k0) of front s.  Callers load it
+// early (three dependent loads: first pivot, diagonal position, value) so that the latency is off the
+// pivot chain.
+__device__ __forceinline__ double block_threshold(int s, int k0, const int32_t* __restrict__ first,
+                                                  const int32_t* __restrict__ ncol, const PivotRef& pr) {
+    const int lane = threadIdx.x % 64;
+    return lane < min(TB, ncol[s] - k0) ? pr.thresh(first[s] + k0 + lane) : 0.0;
+}
+
+__device__ __forceinline__ void potrf_block(int s, int k0, int slot, const int32_t* __restrict__ first,
+                                            const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
+                                            const int64_t* __restrict__ foff, double* __restrict__ fronts,
+                                            double* __restrict__ ldiag, double* __restrict__ rdiag,
+                                            int32_t* __restrict__ status, double thr, double* colbuf,
+                                            int* flags) {
+    const int lane = threadIdx.x % 64;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+    const int m = mrows[s];
+    const int kb = min(TB, ncol[s] - k0);
+    double* F = fronts + foff[s] + (int64_t)k0 + (int64_t)m * k0;
+    const int p0 = first[s] + k0;
+    int* badmin = flags;
+    int* ready = flags + 1;
+    if (threadIdx.x == 0) {
+        *badmin = INT_MAX;
+        *ready = 0;
+    }
+    double a[PW];
+#pragma unroll
+    for (int c = 0; c < PW; c++) {
+        const int j = PW * w + c;
+        a[c] = (j < kb && lane < kb) ? (j <= lane ? F[lane + (int64_t)m * j] : 0.0) : (j == lane ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    // columns of the waves before this one, in order, each as soon as the counter covers it (bounded: the
+    // producing waves belong to this work-group and always progress)
+    int avail = 0;
+    for (int k = 0; k < PW * w; k++) {
+        if (avail <= k) {
+            int spins = 0;
+            do {
+                avail = __hip_atomic_load(ready, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            } while (avail <= k && ++spins < (1 << 22));
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        }
+        const double l0 = colbuf[TB * k + lane];
+#pragma unroll
+        for (int q = 0; q < PW / 2; q++) {
+            const double2 u = *reinterpret_cast<const double2*>(&colbuf[TB * k + PW * w + 2 * q]);
+            a[2 * q] = fma(-l0, u.x, a[2 * q]);
+            a[2 * q + 1] = fma(-l0, u.y, a[2 * q + 1]);
+        }
+    }
+    double myrinv = 1.0;
+    int bad;
+    switch (w) {
+        case 0: bad = potrf_own<0>(a, thr, colbuf, ready, myrinv); break;
+        case 1: bad = potrf_own<1>(a, thr, colbuf, ready, myrinv); break;
+        case 2: bad = potrf_own<2>(a, thr, colbuf, ready, myrinv); break;
+        default: bad = potrf_own<3>(a, thr, colbuf, ready, myrinv); break;
     }
     if (lane == 0 && bad < kb) atomicMin(badmin, bad);
     // results: the front (valid lower part), the compact copy and the reciprocal pivots
@@ -381,9 +417,10 @@ __global__ __launch_bounds__(NT) void blk_potrf(const int32_t* __restrict__ it, 
                                                 double* __restrict__ ldiag, double* __restrict__ rdiag,
                                                 int32_t* __restrict__ status, PivotRef pr) {
     __shared__ __attribute__((aligned(16))) double colbuf[TB * TB];
-    __shared__ int badmin;
-    potrf_block(it[2 * blockIdx.x], it[2 * blockIdx.x + 1], blockIdx.x, first, ncol, mrows, foff, fronts, ldiag,
-                rdiag, status, pr, colbuf, &badmin);
+    __shared__ int flags[2];
+    const int s = it[2 * blockIdx.x], k0 = it[2 * blockIdx.x + 1];
+    potrf_block(s, k0, blockIdx.x, first, ncol, mrows, foff, fronts, ldiag, rdiag, status,
+                block_threshold(s, k0, first, ncol, pr), colbuf, flags);
 }
 
 constexpr int TR = 64;  // panel rows per work-group of the panel solve
@@ -464,7 +501,7 @@ __global__ __launch_bounds__(NT) void blk_trsm_mma(const int32_t* __restrict__ i
             }
 }
 constexpr int KC = 16;
-constexpr int KH = 32;  // panel columns staged in LDS at a time
+constexpr int KH = 16;  // panel columns staged in LDS at a time
 
 // Item: (front, k0, first row ri0, first column rj0) of a tile of up to 128 rows and cw columns.  The
 // accumulators start from the tile of C and the row panel is negated on its way into LDS, so the MFMAs
@@ -506,20 +543,33 @@ __device__ __forceinline__ void tile_mma(double* __restrict__ F, int m, int ri0,
                 acc[a][b][r] = (active && i < nri && j < nrj && gi >= gj) ? F[(int64_t)gi + (int64_t)m * gj] : 0.0;
             }
     // the panel slices go through LDS in halves of KH columns (columns past kb are zero; a half that starts
-    // at or past kb is skipped)
+    // at or past kb is skipped).  Each half is fetched into registers while the previous half's MFMAs run,
+    // then written to LDS, so the panel loads' latency hides under the arithmetic.
+    constexpr int PER = ST * KH / NT;  // panel entries per thread per half (each of Pi and Pj)
+    double fa[PER], fb[PER];
+    auto fetch = [&](int h0) {
+#pragma unroll
+        for (int q = 0; q < PER; q++) {
+            const int e = threadIdx.x + q * NT;
+            const int r = e % ST, t = e / ST;
+            const bool in = h0 + t < kb;
+            const int64_t col = (int64_t)m * (k0 + h0 + t);
+            fa[q] = (in && r < nri) ? F[(int64_t)(ri0 + r) + col] : 0.0;
+            fb[q] = (in && r < nrj) ? F[(int64_t)(rj0 + r) + col] : 0.0;
+        }
+    };
+    fetch(0);
     for (int h0 = 0; h0 < kb; h0 += KH) {
         __syncthreads();  // earlier readers of LDS (this tile's previous half, or the previous item) are done
-        for (int e = threadIdx.x; e < ST * KH; e += NT) {
+#pragma unroll
+        for (int q = 0; q < PER; q++) {
+            const int e = threadIdx.x + q * NT;
             const int r = e % ST, t = e / ST;
-            double av = 0.0, bv = 0.0;
-            if (h0 + t < kb) {
-                if (r < nri) av = F[(int64_t)(ri0 + r) + (int64_t)m * (k0 + h0 + t)];
-                if (r < nrj) bv = F[(int64_t)(rj0 + r) + (int64_t)m * (k0 + h0 + t)];
-            }
-            lds[t * (ST + 1) + r] = -av;
-            lds[KH * (ST + 1) + t * (ST + 1) + r] = bv;
+            lds[t * (ST + 1) + r] = -fa[q];
+            lds[KH * (ST + 1) + t * (ST + 1) + r] = fb[q];
         }
         __syncthreads();
+        if (h0 + KH < kb) fetch(h0 + KH);
         if (active) {
 #pragma unroll 2
             for (int t0 = 0; t0 < KH; t0 += KC) {
@@ -571,7 +621,7 @@ __global__ __launch_bounds__(NT, 2) void blk_syrk(const int32_t* __restrict__ it
     // 64 x 64 column buffer
     __shared__ __attribute__((aligned(16))) double lds[2 * KH * (ST + 1)];
     static_assert(2 * KH * (ST + 1) >= TB * TB, "the column buffer of the diagonal-block Cholesky fits");
-    __shared__ int badmin;
+    __shared__ int flags[2];
     for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
         const int s = it[4 * item], k0 = it[4 * item + 1];
         const int ri0 = it[4 * item + 2], rj0 = it[4 * item + 3];
@@ -579,14 +629,15 @@ __global__ __launch_bounds__(NT, 2) void blk_syrk(const int32_t* __restrict__ it
         const int kb = min(kw, ncol[s] - k0);
         double* F = fronts + foff[s];
         const int nri = min(ST, m - ri0);
+        const int ps = pslot ? pslot[item] : -1;
+        const double thr = ps >= 0 ? block_threshold(s, rj0, first, ncol, pr) : 0.0;  // loaded before the tile
         if (item < nnext)
             tile_mma<2, 4>(F, m, ri0, rj0, nri, min(TB, m - rj0), k0, kb, lds);
         else
             tile_mma<4, 4>(F, m, ri0, rj0, nri, min(ST, m - rj0), k0, kb, lds);
-        if (pslot && pslot[item] >= 0) {
+        if (ps >= 0) {
             __syncthreads();  // the tile's stores are visible to the whole work-group; LDS is free
-            potrf_block(s, rj0, pslot[item], first, ncol, mrows, foff, fronts, ldiag, rdiag, status, pr, lds,
-                        &badmin);
+            potrf_block(s, rj0, ps, first, ncol, mrows, foff, fronts, ldiag, rdiag, status, thr, lds, flags);
         }
     }
 }
@@ -678,7 +729,7 @@ __global__ __launch_bounds__(NT, 2) void dense_front(int64_t t0, int64_t t1, Den
     __shared__ __attribute__((aligned(16))) double Pa[DT * LDT];
     __shared__ __attribute__((aligned(16))) double Pb[DT * LDT];
     __shared__ double inv[4][16][17];
-    __shared__ int task_sh, ok_sh, badmin;
+    __shared__ int task_sh, ok_sh, flags[2];
     static_assert(DT * LDT >= TB * TB, "the column buffer of the diagonal-block Cholesky fits");
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
     const int li = lane % 16, lk = lane / 16;
@@ -775,7 +826,8 @@ __global__ __launch_bounds__(NT, 2) void dense_front(int64_t t0, int64_t t1, Den
                             if (i < nri && j < nrj && i >= j) F[(int64_t)(ri0 + i) + (int64_t)m * (rj0 + j)] = acc[a][b][r];
                         }
             __syncthreads();  // the tile's stores are visible to the work-group; LDS is free
-            potrf_block(s, rj0, slot, first, ncol, mrows, foff, fronts, D.tdiag, D.trdiag, status, pr, Pa, &badmin);
+            potrf_block(s, rj0, slot, first, ncol, mrows, foff, fronts, D.tdiag, D.trdiag, status,
+                        block_threshold(s, rj0, first, ncol, pr), Pa, flags);
             publish_final(myflag, epoch);
             continue;
         }
@@ -1188,6 +1240,9 @@ __global__ __launch_bounds__(NT) void wide_bwd(int s, double* __restrict__ zx, i
 }  // namespace
 
 // ------------------------------------------------------------------------ host side
+namespace opf {
+void chol_set_stream(chol_sym* C, hipStream_t st);
+}
 static void build_numeric_plan(chol_sym* C, const std::vector<int32_t>& colptr, const std::vector<int32_t>& rowind) {
     const Symbolic& S = C->S;
     const int ns = S.nsuper, n = S.n;
@@ -1610,6 +1665,8 @@ static void build_numeric_plan(chol_sym* C, const std::vector<int32_t>& colptr, 
         }
     C->dev.alloc(C->zx, std::max<int64_t>(nflags, 1) * SB);
     C->dev.upload(C->sfault, std::vector<int32_t>(1, 0));
+    C->dev.upload(C->level_d, C->h_level);
+    C->dev.alloc(C->statwords, 1);
 }
 
 extern "C" void chol_default_options(chol_options* o) {
@@ -1753,6 +1810,8 @@ static int dense_grid(chol_sym* C) {
 // the launch sequence (stream capture, thread-local mode) and instantiates it, later calls replay it with one
 // graph launch.  Every captured node is a kernel (no memset or copy nodes); timing mode and the dependency-
 // driven tile path (whose launch carries a per-factorization epoch) run uncaptured.
+static std::atomic<int64_t> g_graph_captures{0}, g_graph_fallbacks{0};
+
 template <class F>
 static void run_graph(chol_sym* C, hipStream_t st, const void* a, const void* b, double tol, F&& enqueue) {
     const bool tiles = !C->lvl_dense_ptr.empty() && C->lvl_dense_ptr.back() > 0;
@@ -1765,21 +1824,45 @@ static void run_graph(chol_sym* C, hipStream_t st, const void* a, const void* b,
             OPF_HIP(hipGraphLaunch(g.exec, st));
             return;
         }
-    OPF_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    try {
-        enqueue();
-    } catch (...) {
+    g_graph_captures.fetch_add(1, std::memory_order_relaxed);
+    // A capture that fails (another thread's work can invalidate it) is abandoned and the sequence is
+    // enqueued directly instead: the graph only saves launch overhead.  Captured work never runs, so the
+    // direct enqueue is the only execution.
+    auto abandon = [&] {
+        g_graph_fallbacks.fetch_add(1, std::memory_order_relaxed);
         hipGraph_t bad = nullptr;
         (void)hipStreamEndCapture(st, &bad);
         if (bad) (void)hipGraphDestroy(bad);
-        throw;
+        (void)hipGetLastError();  // clear the thread's error state for the launches that follow
+    };
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        abandon();
+        enqueue();
+        return;
+    }
+    try {
+        enqueue();
+    } catch (...) {
+        abandon();
+        enqueue();  // an error that is not the capture's comes back from the direct enqueue
+        return;
     }
     hipGraph_t graph = nullptr;
-    OPF_HIP(hipStreamEndCapture(st, &graph));
+    if (hipStreamEndCapture(st, &graph) != hipSuccess || !graph) {
+        if (graph) (void)hipGraphDestroy(graph);
+        abandon();
+        enqueue();
+        return;
+    }
     hipGraphExec_t exec = nullptr;
     const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
-    OPF_HIP(e);
+    if (e != hipSuccess) {
+        g_graph_fallbacks.fetch_add(1, std::memory_order_relaxed);
+        (void)hipGetLastError();
+        enqueue();
+        return;
+    }
     if (C->graphs.size() >= 8) {
         (void)hipGraphExecDestroy(C->graphs.front().exec);
         C->graphs.erase(C->graphs.begin());
@@ -1789,6 +1872,7 @@ static void run_graph(chol_sym* C, hipStream_t st, const void* a, const void* b,
 }
 
 void chol_factor_enqueue(chol_sym* C, const double* kval, hipStream_t st, double pivot_tol) {
+    chol_set_stream(C, st);  // first use: the uploads go on the caller's stream
     C->dev.run();
     const PivotRef pr{kval, C->kdiagpos.p, pivot_tol};
     C->epoch++;
@@ -1865,31 +1949,54 @@ __global__ void init_status(int ns, const int32_t* __restrict__ mrows, int32_t* 
     if (s < ns && mrows[s] > TB) status[s] = INT_MAX;
 }
 
+// The reported pivot: the smallest (level, pivot) over the supernodes' first rejected pivots (an order-free
+// minimum, so the result does not depend on the schedule), one work-group.
+constexpr int SMIN_NT = 1024;
+__global__ __launch_bounds__(SMIN_NT) void status_min(int ns, const int32_t* __restrict__ status,
+                                                      const int32_t* __restrict__ level, int64_t* __restrict__ out) {
+    __shared__ int64_t red[SMIN_NT / 64];
+    int64_t v = INT64_MAX;
+    for (int s = threadIdx.x; s < ns; s += SMIN_NT)
+        if (status[s] != INT_MAX) v = min(v, ((int64_t)level[s] << 32) | (uint32_t)status[s]);
+    for (int o = 32; o > 0; o >>= 1) v = min(v, (int64_t)__shfl_xor((long long)v, o));
+    if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < SMIN_NT / 64; w++) v = min(v, red[w]);
+        out[0] = v;
+    }
+}
+
+static int64_t* host_words(chol_sym* C) {
+    if (!C->hwords) {
+        OPF_HIP(hipHostMalloc((void**)&C->hwords, 4 * sizeof(int64_t)));
+        C->own_hwords = true;
+    }
+    return C->hwords;
+}
+
 // Factor and report: returns -1 if positive definite, else the bad pivot.
 int chol_factor_sync(chol_sym* C, const double* kval, hipStream_t st, double pivot_tol) {
+    chol_set_stream(C, st);  // first use: the uploads go on the caller's stream
     C->dev.run();
     const int ns = C->S.nsuper;
     run_graph(C, st, kval, nullptr, pivot_tol, [&] {
         hipLaunchKernelGGL(init_status, dim3(ceil_div(ns, 256)), dim3(256), 0, st, ns, C->mrows.p, C->status.p);
         OPF_LAUNCH_CHECK();
         chol_factor_enqueue(C, kval, st, pivot_tol);
+        hipLaunchKernelGGL(status_min, dim3(1), dim3(SMIN_NT), 0, st, ns, C->status.p, C->level_d.p, C->statwords.p);
+        OPF_LAUNCH_CHECK();
     });
-    std::vector<int32_t> stat(ns);
-    OPF_HIP(hipMemcpyAsync(stat.data(), C->status.p, ns * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    int32_t ffault = 0;
-    OPF_HIP(hipMemcpyAsync(&ffault, C->ffault.p, sizeof ffault, hipMemcpyDeviceToHost, st));
+    int64_t* hw = host_words(C);
+    hw[1] = 0;  // the fault word fills its low half
+    OPF_HIP(hipMemcpyAsync(hw, C->statwords.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    OPF_HIP(hipMemcpyAsync(hw + 1, C->ffault.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     OPF_HIP(hipStreamSynchronize(st));
     tcollect(C);
+    const int64_t key = hw[0];
+    const int32_t ffault = (int32_t)hw[1];
     OPF_CHECK(ffault == 0, OPF_E_DEVICE, "chol_factor: a dense-front tile wait exceeded its bound");
-    int bad_level = INT_MAX, bad = -1;
-    for (int s = 0; s < ns; s++)
-        if (stat[s] != INT_MAX) {
-            int l = C->h_level[s];
-            if (l < bad_level || (l == bad_level && stat[s] < bad)) {
-                bad_level = l;
-                bad = stat[s];
-            }
-        }
+    const int bad = key == INT64_MAX ? -1 : (int)(key & 0xffffffff);
     C->factored = bad < 0;
     return bad;
 }
@@ -1964,6 +2071,7 @@ static void solve_enqueue(chol_sym* C, const double* b, double* x, hipStream_t s
 }
 
 void chol_solve_enqueue(chol_sym* C, const double* b, double* x, hipStream_t st) {
+    chol_set_stream(C, st);  // first use: the uploads go on the caller's stream
     C->dev.run();
     run_graph(C, st, b, x, -1.0, [&] { solve_enqueue(C, b, x, st, handle_bufs(C)); });
 }
@@ -1974,8 +2082,16 @@ void chol_use_graphs(chol_sym* C, bool on) { C->use_graphs = on; }
 // The analysis's device buffers and uploads, normally performed at the first factorization, done now.
 void chol_prepare_device(chol_sym* C) { C->dev.run(); }
 
+// The fault word of the last sweeps (0 when no front took the sync-free solves), read through the pinned
+// host words when the handle has them (the allocation-free solve must not allocate them).
 static int read_fault(const chol_sym* C, const int32_t* fault, hipStream_t st) {
     if (C->h_flag_off.empty()) return 0;
+    if (C->hwords) {
+        C->hwords[2] = 0;
+        OPF_HIP(hipMemcpyAsync(C->hwords + 2, fault, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        OPF_HIP(hipStreamSynchronize(st));
+        return (int32_t)C->hwords[2];
+    }
     int32_t v = 0;
     OPF_HIP(hipMemcpyAsync(&v, fault, sizeof v, hipMemcpyDeviceToHost, st));
     OPF_HIP(hipStreamSynchronize(st));
@@ -1984,12 +2100,32 @@ static int read_fault(const chol_sym* C, const int32_t* fault, hipStream_t st) {
 
 int chol_solve_fault(chol_sym* C, hipStream_t st) { return read_fault(C, C->sfault.p, st); }
 
+// Pending device uploads of the analysis run on st (when they have not run yet).
+void chol_set_stream(chol_sym* C, hipStream_t st) {
+    if (!C->dev.done) C->dev.stream = st;
+}
+
+// Lends the factorization 4 int64 words of pinned host memory (owned by the caller, who outlives C).
+void chol_bind_host(chol_sym* C, int64_t* words) {
+    if (C->own_hwords && C->hwords) (void)hipHostFree(C->hwords);
+    C->hwords = words;
+    C->own_hwords = false;
+}
+
 __global__ void fill_i32(int n, int32_t v, int32_t* __restrict__ p) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
 }
 
 }  // namespace opf
+
+extern "C" int chol_graph_stats(int64_t* captures, int64_t* fallbacks) {
+    return guarded([&] {
+        OPF_CHECK(captures && fallbacks, OPF_E_INVALID, "chol_graph_stats: null argument");
+        *captures = g_graph_captures.load();
+        *fallbacks = g_graph_fallbacks.load();
+    });
+}
 
 extern "C" int chol_factor(chol_sym* C, const double* kval, void* stream, int32_t* bad_col) {
     return guarded([&] {

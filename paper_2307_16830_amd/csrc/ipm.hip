@@ -28,6 +28,8 @@ void chol_solve_enqueue(chol_sym* C, const double* b, double* x, hipStream_t st)
 int chol_solve_fault(chol_sym* C, hipStream_t st);
 void chol_prepare_device(chol_sym* C);
 void chol_use_graphs(chol_sym* C, bool on);
+void chol_bind_host(chol_sym* C, int64_t* words);
+void chol_set_stream(chol_sym* C, hipStream_t st);
 }  // namespace opf
 
 using namespace opf;
@@ -611,6 +613,9 @@ int ipm_create_ex(opf_model* M, const ipm_options* opts, const chol_options* cop
             }
             // graphs need a stream of our own to capture on (capture on the null stream is not allowed)
             chol_use_graphs(S->C, S->o.graphs != 0 && S->st != nullptr);
+            // pending uploads of the analysis (and of a model created without a stream) run on this stream
+            chol_set_stream(S->C, S->st);
+            if (!M->dev.done && !M->dev.stream) M->dev.stream = S->st;
             for (DBuf<double>* b : {&S->x, &S->zl, &S->zu, &S->xl, &S->xu, &S->g, &S->jty, &S->Sx, &S->dxl, &S->dxu,
                                     &S->qx, &S->rhs, &S->tmp_n, &S->wdx, &S->jtdy, &S->xt})
                 b->alloc(n);
@@ -643,6 +648,8 @@ int ipm_create_ex(opf_model* M, const ipm_options* opts, const chol_options* cop
             } else {
                 OPF_HIP(hipHostMalloc((void**)&S->host, 16 * sizeof(double)));
             }
+            // the reductions read at most 8 doubles; the last four words carry the factorization's status
+            chol_bind_host(S->C, reinterpret_cast<int64_t*>(S->host + 12));
             if (events) {
                 for (int q = 0; q < 10; q++) S->ev[q] = events[q];
                 S->own_events = false;
@@ -1110,10 +1117,12 @@ extern "C" int ipm_solve(ipm_state* S, ipm_result* out) {
 extern "C" int ipm_get_iterate(const ipm_state* S, double* x, double* s, double* y) {
     return guarded([&] {
         OPF_CHECK(S, OPF_E_INVALID, "ipm_get_iterate: null state");
+        // every copy on the state's own stream: an operation on the legacy null stream would have to order
+        // itself after other threads' streams, which fails while one of them is capturing a graph
+        if (x) OPF_HIP(hipMemcpyAsync(x, S->x.p, S->n * 8, hipMemcpyDeviceToHost, S->st));
+        if (s) OPF_HIP(hipMemcpyAsync(s, S->s.p, S->m * 8, hipMemcpyDeviceToHost, S->st));
+        if (y) OPF_HIP(hipMemcpyAsync(y, S->y.p, S->m * 8, hipMemcpyDeviceToHost, S->st));
         OPF_HIP(hipStreamSynchronize(S->st));
-        if (x) OPF_HIP(hipMemcpy(x, S->x.p, S->n * 8, hipMemcpyDeviceToHost));
-        if (s) OPF_HIP(hipMemcpy(s, S->s.p, S->m * 8, hipMemcpyDeviceToHost));
-        if (y) OPF_HIP(hipMemcpy(y, S->y.p, S->m * 8, hipMemcpyDeviceToHost));
     });
 }
 
@@ -1121,9 +1130,8 @@ extern "C" int ipm_get_state(const ipm_state* S, double* x, double* s, double* y
                              double* vu, double* mu, double* dw_last) {
     return guarded([&] {
         OPF_CHECK(S, OPF_E_INVALID, "ipm_get_state: null state");
-        OPF_HIP(hipStreamSynchronize(S->st));
         auto get = [&](double* h, const DBuf<double>& d, int len) {
-            if (h) OPF_HIP(hipMemcpy(h, d.p, (size_t)len * 8, hipMemcpyDeviceToHost));
+            if (h) OPF_HIP(hipMemcpyAsync(h, d.p, (size_t)len * 8, hipMemcpyDeviceToHost, S->st));
         };
         get(x, S->x, S->n);
         get(s, S->s, S->m);
@@ -1132,6 +1140,7 @@ extern "C" int ipm_get_state(const ipm_state* S, double* x, double* s, double* y
         get(zu, S->zu, S->n);
         get(vl, S->vl, S->m);
         get(vu, S->vu, S->m);
+        OPF_HIP(hipStreamSynchronize(S->st));
         if (mu) *mu = S->mu;
         if (dw_last) *dw_last = S->dw_last;
     });
@@ -1166,11 +1175,12 @@ extern "C" int ipm_direction(ipm_state* S, double* dx, double* ds, double* dy, d
         ipm_iter_info I{};
         status = compute_direction(S, S->mu, I);
         if (status != OPF_OK) return;
-        OPF_HIP(hipStreamSynchronize(S->st));
         double* outs[7] = {dx, ds, dy, dzl, dzu, dvl, dvu};
         const int lens[7] = {S->n, S->m, S->m, S->n, S->n, S->m, S->m};
         for (int q = 0; q < 7; q++)
-            if (outs[q]) OPF_HIP(hipMemcpy(outs[q], S->d[q].p, (size_t)lens[q] * 8, hipMemcpyDeviceToHost));
+            if (outs[q])
+                OPF_HIP(hipMemcpyAsync(outs[q], S->d[q].p, (size_t)lens[q] * 8, hipMemcpyDeviceToHost, S->st));
+        OPF_HIP(hipStreamSynchronize(S->st));
         if (delta_w) *delta_w = I.delta_w;
         if (ir_steps) *ir_steps = I.ir_steps;
     });

@@ -14,6 +14,7 @@
 // completion synchronizes the device under the others.  With ipm_options.graphs each solve's factorization
 // and triangular solves are captured once on the slot's stream and replayed.
 #include <algorithm>
+#include <cstdio>
 #include <array>
 #include <chrono>
 #include <condition_variable>
@@ -147,6 +148,8 @@ namespace {
 
 void finish(opf_server* S, Done&& d) {
     const int64_t tag = d.r.tag;
+    // a failed request carries the message its failure left on this worker thread
+    if (d.r.status < 0) snprintf(d.r.message, sizeof d.r.message, "%s", opf_last_error());
     S->active.erase(tag);
     S->done[tag] = std::move(d);
     S->ready.push_back(tag);

@@ -28,7 +28,7 @@ EXPORTED = [
     "opf_last_error", "opf_default_options", "opf_create", "opf_destroy", "opf_dims", "opf_structure", "opf_bounds", "opf_initial_point",
     "opf_eval_derivs", "kkt_pattern", "kkt_condense", "chol_default_options", "chol_analyze", "chol_destroy",
     "chol_info", "chol_perm", "chol_etree", "chol_supernodes", "chol_supernode_rows", "chol_factor", "chol_solve",
-    "chol_solve_noalloc",
+    "chol_solve_noalloc", "chol_graph_stats",
     "chol_export_factor", "ipm_default_options", "ipm_create", "ipm_destroy", "ipm_step", "ipm_solve",
     "ipm_get_iterate", "ipm_chol", "ipm_get_state", "ipm_set_state", "ipm_direction", "chol_timing",
     "chol_timing_read", "serve_default_options", "opf_serve_create", "opf_serve_submit", "opf_serve_poll",
@@ -86,10 +86,12 @@ class ServeResult(ctypes.Structure):
     _fields_ = [("tag", ctypes.c_int64), ("status", ctypes.c_int32), ("iterations", ctypes.c_int32),
                 ("objective", ctypes.c_double), ("n", ctypes.c_int32), ("m", ctypes.c_int32),
                 ("footprint", ctypes.c_int64), ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
-                ("t_done", ctypes.c_double)]
+                ("t_done", ctypes.c_double), ("message", ctypes.c_char * 160)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["message"] = d["message"].decode(errors="replace")
+        return d
 
 
 class IterInfo(ctypes.Structure):
@@ -137,6 +139,7 @@ def lib():
         L.chol_factor.argtypes = [VP, VP, VP, I32P]
         L.chol_solve.argtypes = [VP, VP, VP, ctypes.c_int32, VP]
         L.chol_solve_noalloc.argtypes = [VP, VP, VP, ctypes.c_int32, VP]
+        L.chol_graph_stats.argtypes = [ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
         L.chol_export_factor.argtypes = [VP, I64P, I32P, F64P]
         L.chol_timing.argtypes = [VP, ctypes.c_int]
         L.chol_timing_read.argtypes = [VP, F64P, I64P, F64P, F64P]
@@ -467,6 +470,14 @@ class IPM:
         x, s, y = np.zeros(self.model.n), np.zeros(self.model.m), np.zeros(self.model.m)
         _check(lib().ipm_get_iterate(self._h, _p(x, F64P), _p(s, F64P), _p(y, F64P)), "ipm_get_iterate")
         return x, s, y
+
+
+def graph_stats():
+    """(captures, fallbacks): launch sequences captured into HIP graphs so far in this process, and captures that
+    failed and ran as plain launches instead."""
+    c, f = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().chol_graph_stats(ctypes.byref(c), ctypes.byref(f)), "chol_graph_stats")
+    return c.value, f.value
 
 
 def status_name(rc):

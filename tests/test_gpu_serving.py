@@ -62,7 +62,7 @@ def test_results_equal_alone_and_in_the_mix():
     for tag, g in grids:
         r = res[tag]
         s0, it0, obj0, x0 = alone[tag]
-        assert r["status"] == s0, (tag, r["status"], s0)
+        assert r["status"] == s0, (tag, r["status"], s0, r["message"])
         assert r["iterations"] == it0, (tag, r["iterations"], it0)
         x = srv.x(tag, r["n"])
         assert np.max(np.abs(x - x0)) <= 1e-12 * max(1.0, np.max(np.abs(x0))), tag
@@ -120,3 +120,30 @@ def test_reused_tag_is_rejected():
     with pytest.raises(opf().OpfError):
         srv.submit(g, tag)  # holds a result
     srv.close()
+
+
+def test_null_stream_work_beside_the_server_fails_no_request():
+    """The server's workers capture their factorization and solve launches into graphs on their own streams
+    while the caller keeps the legacy null stream busy (torch's default stream here): every request must
+    still converge, with the statuses and iteration counts of the one-at-a-time path (a capture that another
+    thread invalidates is abandoned and its launches are enqueued directly)."""
+    grids = trace_grids(12, 900)
+    alone = {tag: solve_alone(g) for tag, g in grids}
+    srv = opf().Server(slots=6, hbm_budget=2 << 30)
+    for tag, g in grids:
+        srv.submit(g, tag)
+    a = torch.ones(1 << 20, dtype=torch.float64, device="cuda")
+    res = {}
+    deadline = time.time() + 90.0
+    while len(res) < len(grids):
+        assert time.time() < deadline, f"only {len(res)} of {len(grids)} results after 90 s"
+        for _ in range(20):  # null-stream work and synchronous copies while requests are in flight
+            a.mul_(1.0000001)
+            float(a[:16].sum().item())
+        for r in srv.poll(wait=False):
+            res[r["tag"]] = r
+    srv.close()
+    for tag, g in grids:
+        s0, it0, _, _ = alone[tag]
+        assert res[tag]["status"] == s0, (tag, res[tag]["status"], res[tag]["message"])
+        assert res[tag]["iterations"] == it0
