@@ -168,9 +168,11 @@ typedef struct {
      * disables it: experimental, its first device run did not complete */
     int32_t tile_min;
     /* a level whose only blocked front has at least pair_min pivots pairs
-     * its 64-column panels: the first panel of a pair updates only the
+     * its leading 64-column panels, as long as a pair leaves at least
+     * pair_min rows below it: the first panel of a pair updates only the
      * second one's columns, the second applies both to the rest of the front
-     * as one rank-128 update; 0 (default): never */
+     * as one rank-128 update (half the passes over the trailing matrix);
+     * default 2048, 0: never */
     int32_t pair_min;
 } chol_options;
 

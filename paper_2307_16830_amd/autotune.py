@@ -23,12 +23,12 @@ INT_MAX = 2 ** 31 - 1
 
 # candidate settings: the defaults first (ties keep them)
 CANDIDATES = [
-    dict(zero_abs=64, zero_rel=0.05, max_width=INT_MAX, pair_min=0),
-    dict(zero_abs=16, zero_rel=0.02, max_width=INT_MAX, pair_min=0),
-    dict(zero_abs=256, zero_rel=0.10, max_width=INT_MAX, pair_min=0),
-    dict(zero_abs=1024, zero_rel=0.20, max_width=INT_MAX, pair_min=0),
-    dict(zero_abs=64, zero_rel=0.05, max_width=256, pair_min=0),
-    dict(zero_abs=64, zero_rel=0.05, max_width=INT_MAX, pair_min=1024),
+    dict(zero_abs=64, zero_rel=0.05, max_width=INT_MAX, pair_min=2048),
+    dict(zero_abs=16, zero_rel=0.02, max_width=INT_MAX, pair_min=2048),
+    dict(zero_abs=256, zero_rel=0.10, max_width=INT_MAX, pair_min=2048),
+    dict(zero_abs=1024, zero_rel=0.20, max_width=INT_MAX, pair_min=2048),
+    dict(zero_abs=64, zero_rel=0.05, max_width=256, pair_min=2048),
+    dict(zero_abs=64, zero_rel=0.05, max_width=INT_MAX, pair_min=512),
 ]
 
 

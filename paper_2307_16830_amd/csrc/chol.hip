@@ -444,6 +444,7 @@ __global__ __launch_bounds__(NT) void blk_trsm_mma(const int32_t* __restrict__ i
                                                    const int64_t* __restrict__ foff, const double* __restrict__ ldiag,
                                                    const double* __restrict__ rdiag, double* __restrict__ fronts) {
     __shared__ double inv[4][16][17];  // inv[b][p][q] = inv(L_bb)[p][q]
+    __shared__ double dg[4][16][17];   // dg[b][t][p] = L_bb(p, t), staged with vector loads
     const int s = it[4 * blockIdx.x], k0 = it[4 * blockIdx.x + 1], rb = it[4 * blockIdx.x + 2];
     const int slot = it[4 * blockIdx.x + 3];
     const int m = mrows[s];
@@ -453,14 +454,19 @@ __global__ __launch_bounds__(NT) void blk_trsm_mma(const int32_t* __restrict__ i
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
     const int li = lane % 16, lk = lane / 16;
     {
+        // the wave's diagonal block into LDS in one round of loads (rows of a column are contiguous), then
+        // the substitution reads it as broadcasts
         const int b = wave, q = li;  // the four 16-lane groups compute the same columns; group 0 stores
+#pragma unroll
+        for (int r = 0; r < 4; r++) dg[b][4 * r + lk][li] = Lc[(16 * b + li) + TB * (16 * b + 4 * r + lk)];
+        const double rp = lane < 16 ? rc[16 * b + lane] : 0.0;
         double y[16];
 #pragma unroll
         for (int p = 0; p < 16; p++) {
             double acc = p == q ? 1.0 : 0.0;
 #pragma unroll
-            for (int t = 0; t < p; t++) acc -= Lc[(16 * b + p) + TB * (16 * b + t)] * y[t];
-            y[p] = acc * rc[16 * b + p];
+            for (int t = 0; t < p; t++) acc -= dg[b][t][p] * y[t];
+            y[p] = acc * lane_value(rp, p);
         }
         if (lk == 0)
 #pragma unroll
@@ -1512,14 +1518,17 @@ static void build_numeric_plan(chol_sym* C, const std::vector<int32_t>& colptr, 
             }
         }
         const bool paired = nblocked == 1 && C->opts.pair_min > 0 && C->h_ncol[only] >= C->opts.pair_min;
+        // pairs cover the leading steps whose pair still leaves at least pair_min rows below it (where the
+        // update is bound by passes over a large trailing matrix); the later, latency-bound steps are single
+        int npair_steps = 0;
+        if (paired) {
+            const int nn = C->h_ncol[only], m = C->h_mrows[only];
+            while ((npair_steps + 2) * TB < nn && m - (npair_steps + 2) * TB >= C->opts.pair_min) npair_steps += 2;
+        }
         for (int k = 0; k < maxsteps; k++) {
             // pairing: step kind 1 = first panel of a pair, 2 = second panel (rank-128 trailing update)
             int kind = 0;
-            if (paired) {
-                const int nn = C->h_ncol[only];
-                if (k % 2 == 0 && (k + 1) * TB < nn) kind = 1;
-                if (k % 2 == 1) kind = 2;
-            }
+            if (k < npair_steps) kind = k % 2 == 0 ? 1 : 2;
             chol_sym::Step st{l, (int32_t)pot.size() / 2, 0, (int32_t)trs.size() / 4, 0, 0, 0, 0, 0, TB};
             for (int q = C->lvl_ptr[l]; q < C->lvl_ptr[l + 1]; q++) {
                 int s = C->lvl_sn[q];
@@ -1677,7 +1686,7 @@ extern "C" void chol_default_options(chol_options* o) {
     o->zero_rel = 0.05;
     o->pivot_tol = 0.0;
     o->tile_min = 0;
-    o->pair_min = 0;
+    o->pair_min = 2048;
 }
 
 extern "C" int chol_analyze(int32_t n, const int32_t* colptr, const int32_t* rowind, const chol_options* opts,

@@ -305,15 +305,16 @@ def test_ipm_cfg0_matches_oracle(seed):
 @pytest.mark.parametrize("n", [65, 100, 200, 333, 768, 900, 1100, 1300])
 def test_dense_front_blocked_cholesky(n):
     """A dense SPD matrix is one supernode: exercises the blocked path (LDS diagonal block, panel solve, MFMA
-    update), up to fronts of 1,300 pivots; with pair_min = 1,024 a lone front from that size pairs its panels
-    (rank-128 trailing updates), 1,100 ending on a partial pair and 1,300 on an unpaired panel."""
+    update), up to fronts of 1,300 pivots; with pair_min = 512 the fronts of 768 pivots and more pair their
+    leading panels (rank-128 trailing updates) while a pair leaves at least 512 rows below it (4, 6, 8 and 12
+    paired steps), then go on with single panels."""
     rng = np.random.default_rng(n)
     A = rng.normal(size=(n, n))
     K = A @ A.T + n * np.eye(n)
     rows, cols = np.tril_indices(n)
     cp, ri = ochol.lower_csc(n, rows, cols)
     colidx = np.repeat(np.arange(n), np.diff(cp))
-    C = opf().Cholesky(n, cp, ri, opf().chol_options(pair_min=1024))
+    C = opf().Cholesky(n, cp, ri, opf().chol_options(pair_min=512))
     assert C.nsuper == 1
     assert C.factor(dev(K[ri, colidx])) == -1
     lp, li, lx = C.export_factor()
