@@ -95,6 +95,9 @@ struct chol_sym {
     // sync-free solves of wide fronts
     std::vector<int64_t> h_flag_off;  // per supernode (wide fronts only): offset of its blocks in zx
     DBuf<double> zx;                  // solved 64-blocks of the wide fronts' sweeps
+    DBuf<double> winv;                // inverses of the wide fronts' 64 x 64 diagonal blocks (4096 doubles each)
+    DBuf<int32_t> winv_it;            // per block: (supernode, block, block index in winv)
+    int nwinv = 0;
     DBuf<int32_t> sfault;
     Deferred dev;  // pending uploads, run at the first device use
     // optional per-category kernel timing (assemble, small, potrf, trsm, syrk): bit mask of categories
@@ -920,6 +923,7 @@ __global__ void permute_out(int n, const int32_t* __restrict__ perm, const doubl
 }
 
 constexpr int WIDE = 256;  // fronts with at least this many pivots use the sync-free solves
+constexpr int SCB = 16;    // pivot columns per block of the narrow-front sweeps
 
 // Forward sweep for one front: w = b(own rows) + children's partial results; solve with the diagonal
 // block; keep w on the off-diagonal rows as this front's partial result.  w lives in LDS (dynamic, wcap
@@ -957,16 +961,40 @@ __global__ __launch_bounds__(NT) void solve_fwd(const int32_t* __restrict__ list
         for (; t < nu; t += NT) w[rl[t]] += uc[t];
         __syncthreads();
     }
-    // reciprocal pivots first (in parallel), then one multiply and one barrier per pivot column; the solved
-    // values go to zz so that no thread rewrites w[j] while others still read it
-    __shared__ double rdg[WIDE], zz[WIDE];
+    // blocks of SCB pivot columns: wave 0 solves the diagonal block in registers (solved values to zz), then
+    // every thread applies the block's columns to its rows below it, all SCB loads of a row in flight at once.
+    // Each w[i] takes the columns in increasing order, one fused multiply-add each, as a column-by-column
+    // sweep would.
+    __shared__ double zz[WIDE];
     const double* L = fronts + foff[s];
-    for (int j = threadIdx.x; j < nn; j += NT) rdg[j] = 1.0 / L[j + (int64_t)m * j];
-    __syncthreads();
-    for (int j = 0; j < nn; j++) {
-        const double z = w[j] * rdg[j];
-        for (int i = j + 1 + threadIdx.x; i < m; i += NT) w[i] -= L[i + (int64_t)m * j] * z;
-        if (threadIdx.x == 0) zz[j] = z;
+    const int lane = threadIdx.x % 64;
+    for (int j0 = 0; j0 < nn; j0 += SCB) {
+        const int cb = min(SCB, nn - j0);
+        if (threadIdx.x < 64) {
+            const bool act = lane < cb;
+            double a[SCB];  // lane p: a[t] = L(j0 + p, j0 + t), t < p
+#pragma unroll
+            for (int t = 0; t < SCB; t++) a[t] = (act && t < lane) ? L[(j0 + lane) + (int64_t)m * (j0 + t)] : 0.0;
+            double wp = act ? w[j0 + lane] : 0.0;
+            const double rp = act ? 1.0 / L[(j0 + lane) + (int64_t)m * (j0 + lane)] : 1.0;
+#pragma unroll
+            for (int t = 0; t < SCB; t++) {
+                const double z = lane_value(wp, t) * lane_value(rp, t);
+                if (lane > t) wp = fma(-a[t], z, wp);
+                if (lane == t && act) zz[j0 + t] = z;
+            }
+        }
+        __syncthreads();
+        for (int i = j0 + cb + threadIdx.x; i < m; i += NT) {
+            double lv[SCB];
+#pragma unroll
+            for (int t = 0; t < SCB; t++) lv[t] = t < cb ? L[i + (int64_t)m * (j0 + t)] : 0.0;
+            double acc = w[i];
+#pragma unroll
+            for (int t = 0; t < SCB; t++)
+                if (t < cb) acc = fma(-lv[t], zz[j0 + t], acc);
+            w[i] = acc;
+        }
         __syncthreads();
     }
     for (int t = threadIdx.x; t < m; t += NT) {
@@ -1014,21 +1042,55 @@ __global__ __launch_bounds__(NT) void solve_bwd(const int32_t* __restrict__ list
         for (; t < nr; t += NT) xb[t] = y[R[r0 + t]];
         __syncthreads();
         for (int j = wv; j < nn; j += NT / 64) {
+            // four independent partial sums per lane, so that four loads of the column are in flight
             const double* col = L + (int64_t)m * j + r0;
-            double acc = 0.0;
-            for (int t = ln; t < nr; t += 64) acc += col[t] * xb[t];
-            acc = wave_sum(acc);
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+            int t = ln;
+            for (; t + 192 < nr; t += 256) {
+                a0 += col[t] * xb[t];
+                a1 += col[t + 64] * xb[t + 64];
+                a2 += col[t + 128] * xb[t + 128];
+                a3 += col[t + 192] * xb[t + 192];
+            }
+            for (; t < nr; t += 64) a0 += col[t] * xb[t];
+            const double acc = wave_sum((a0 + a1) + (a2 + a3));
             if (ln == 0) w[j] -= acc;
         }
     }
-    // reciprocal pivots in parallel, then one multiply and one barrier per pivot (solved values in xx)
-    __shared__ double rdg[WIDE], xx[WIDE];
-    for (int j = threadIdx.x; j < nn; j += NT) rdg[j] = 1.0 / L[j + (int64_t)m * j];
-    __syncthreads();
-    for (int j = nn - 1; j >= 0; j--) {
-        const double xj = w[j] * rdg[j];
-        for (int i = threadIdx.x; i < j; i += NT) w[i] -= L[j + (int64_t)m * i] * xj;
-        if (threadIdx.x == 0) xx[j] = xj;
+    // the pivot block L11^T in blocks of SCB columns from the last: wave 0 solves the diagonal block in
+    // registers (solved values to xx), then every thread applies the block's values to its earlier rows,
+    // all SCB loads of a row in flight at once.  Each w[i] takes the solved values in decreasing order, one
+    // fused multiply-add each, as a pivot-by-pivot sweep would.
+    __shared__ double xx[WIDE];
+    __syncthreads();  // w of the pivots is complete
+    for (int j1 = nn; j1 > 0; j1 -= SCB) {
+        const int j0 = max(0, j1 - SCB), cb = j1 - j0;
+        if (threadIdx.x < 64) {
+            const bool act = ln < cb;
+            double a[SCB];  // lane q: a[t] = L(j0 + t, j0 + q), t > q
+#pragma unroll
+            for (int t = 0; t < SCB; t++) a[t] = (act && t > ln && t < cb) ? L[(j0 + t) + (int64_t)m * (j0 + ln)] : 0.0;
+            double wq = act ? w[j0 + ln] : 0.0;
+            const double rq = act ? 1.0 / L[(j0 + ln) + (int64_t)m * (j0 + ln)] : 1.0;
+#pragma unroll
+            for (int t = SCB - 1; t >= 0; t--) {
+                if (t >= cb) continue;
+                const double x = lane_value(wq, t) * lane_value(rq, t);
+                if (ln < t) wq = fma(-a[t], x, wq);
+                if (ln == t) xx[j0 + t] = x;
+            }
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < j0; i += NT) {
+            double lv[SCB];
+#pragma unroll
+            for (int t = 0; t < SCB; t++) lv[t] = t < cb ? L[(j0 + t) + (int64_t)m * i] : 0.0;
+            double acc = w[i];
+#pragma unroll
+            for (int t = SCB - 1; t >= 0; t--)
+                if (t < cb) acc = fma(-lv[t], xx[j0 + t], acc);
+            w[i] = acc;
+        }
         __syncthreads();
     }
     for (int j = threadIdx.x; j < nn; j += NT) y[f + j] = xx[j];
@@ -1109,6 +1171,41 @@ __device__ __forceinline__ double take_block_wave(const double* __restrict__ zx,
     return v;
 }
 
+// Inverse of one 64 x 64 diagonal block of a wide front (one wave per block, identity padding past the last
+// pivot), column-major into winv: lane j forms column j by forward substitution, the block and its reciprocal
+// pivots read as broadcasts from LDS.  The sweeps then solve with a block as one product instead of 64
+// dependent steps.
+__global__ __launch_bounds__(64) void wide_inverse(const int32_t* __restrict__ items,
+                                                   const int32_t* __restrict__ ncol,
+                                                   const int32_t* __restrict__ mrows,
+                                                   const int64_t* __restrict__ foff, const double* __restrict__ fronts,
+                                                   double* __restrict__ winv) {
+    __shared__ double Ls[SB * SB];  // Ls[k * 64 + i] = L(i, k) of the block
+    __shared__ double ri[SB];
+    const int s = items[3 * blockIdx.x], g = items[3 * blockIdx.x + 1];
+    const int64_t ob = items[3 * blockIdx.x + 2];
+    const int m = mrows[s], nn = ncol[s];
+    const int r0 = SB * g, nb = min(SB, nn - r0);
+    const double* L = fronts + foff[s] + r0 + (int64_t)m * r0;
+    const int j = threadIdx.x;
+    for (int k = 0; k < SB; k++)
+        Ls[k * SB + j] = (j < nb && k < nb) ? (j >= k ? L[j + (int64_t)m * k] : 0.0) : (j == k ? 1.0 : 0.0);
+    __syncthreads();
+    ri[j] = 1.0 / Ls[j * SB + j];
+    __syncthreads();
+    double x[SB];
+#pragma unroll
+    for (int i = 0; i < SB; i++) {
+        double acc = i == j ? 1.0 : 0.0;
+#pragma unroll
+        for (int k = 0; k < i; k++) acc = fma(-Ls[k * SB + i], x[k], acc);
+        x[i] = acc * ri[i];
+    }
+    double* out = winv + ob * SB * SB + (int64_t)SB * j;  // column j
+#pragma unroll
+    for (int i = 0; i < SB; i++) out[i] = x[i];
+}
+
 // forward sweep of one wide front.  Work-group g < nblk owns pivot rows [64g, 64g + 64): it subtracts
 // L(rows, block c) z_c for every c < g as soon as z_c is in zx, solves with L(g, g) and publishes z_g
 // (to zx, device-coherent, and to y).  The remaining work-groups own 64-row blocks of the rows below
@@ -1119,8 +1216,10 @@ __global__ __launch_bounds__(NT) void wide_fwd(int s, double* __restrict__ zx, i
                                                const int32_t* __restrict__ mrows, const int64_t* __restrict__ foff,
                                                const int64_t* __restrict__ roff, const int64_t* __restrict__ uoff,
                                                const double* __restrict__ fronts, const double* __restrict__ work,
-                                               double* __restrict__ upd, double* __restrict__ y) {
+                                               double* __restrict__ upd, double* __restrict__ y,
+                                               const double* __restrict__ winv) {
     __shared__ double red[NT / 64][SB];
+    __shared__ double wsh[SB];
     const int m = mrows[s], nn = ncol[s], f = first[s];
     const int nblk = (nn + SB - 1) / SB;
     const int g = blockIdx.x;
@@ -1132,16 +1231,11 @@ __global__ __launch_bounds__(NT) void wide_fwd(int s, double* __restrict__ zx, i
     const int i = threadIdx.x % 64, q = threadIdx.x / 64;
     const bool rowok = i < nr;
     const double* Lr = L + (rowok ? r0 + i : 0);  // row r0 + i, column stride m
-    // own diagonal block (row i in registers of wave 0) and reciprocal pivot, read before any wait
-    double a[SB];
-    double rinv = 1.0;
+    // row i of the inverse of the own diagonal block (wave 0, read before any wait; zero above the diagonal)
+    double v[SB];
+    const double* Vi = winv + (int64_t)g * SB * SB + i;  // Vi[64 j] = inv(L_gg)(i, j)
 #pragma unroll
-    for (int j = 0; j < SB; j++) a[j] = (piv && q == 0 && rowok && j < i) ? Lr[(int64_t)m * (r0 + j)] : 0.0;
-    if (piv && q == 0 && rowok) rinv = 1.0 / Lr[(int64_t)m * (r0 + i)];
-    // the row scaled by its reciprocal pivot: the substitution below then runs on u_i = w_i / L_ii with one
-    // broadcast and one FMA per step (entries on and above the diagonal are 0, so no select is needed)
-#pragma unroll
-    for (int j = 0; j < SB; j++) a[j] *= rinv;
+    for (int j = 0; j < SB; j++) v[j] = (piv && q == 0 && j <= i) ? Vi[(int64_t)SB * j] : 0.0;
     const double w0 = (q == 0 && rowok) ? work[roff[s] + r0 + i] : 0.0;  // the right-hand side, also early
     double acc = 0.0;
     bool alive = true;
@@ -1165,10 +1259,17 @@ __global__ __launch_bounds__(NT) void wide_fwd(int s, double* __restrict__ zx, i
         if (rowok) upd[uoff[s] + (r0 - nn) + i] = wi;
         return;
     }
-    double u = wi * rinv;
+    // z_g = inv(L_gg) w_g (rows past the last pivot carry w = 0 and identity rows of the inverse)
+    wsh[i] = wi;  // read back by the other lanes of this wave (LDS keeps a wave's accesses in order)
+    double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
 #pragma unroll
-    for (int j = 0; j < SB; j++)
-        if (j < nr) u = fma(-a[j], lane_value(u, j), u);
+    for (int j = 0; j < SB; j += 4) {
+        p0 = fma(v[j], wsh[j], p0);
+        p1 = fma(v[j + 1], wsh[j + 1], p1);
+        p2 = fma(v[j + 2], wsh[j + 2], p2);
+        p3 = fma(v[j + 3], wsh[j + 3], p3);
+    }
+    const double u = (p0 + p1) + (p2 + p3);
     store_coherent(zx + SB * g + i, rowok ? u : 0.0);
     if (rowok) y[f + r0 + i] = u;
 }
@@ -1181,8 +1282,10 @@ __global__ __launch_bounds__(NT) void wide_bwd(int s, double* __restrict__ zx, i
                                                const int32_t* __restrict__ first, const int32_t* __restrict__ ncol,
                                                const int32_t* __restrict__ mrows, const int64_t* __restrict__ foff,
                                                const int64_t* __restrict__ roff, const int32_t* __restrict__ rows,
-                                               const double* __restrict__ fronts, double* __restrict__ y) {
+                                               const double* __restrict__ fronts, double* __restrict__ y,
+                                               const double* __restrict__ winv) {
     __shared__ double xs[SB];
+    __shared__ double tsh[SB];
     __shared__ double red[NT / 64][SB];
     const int m = mrows[s], nn = ncol[s], f = first[s];
     const int nblk = (nn + SB - 1) / SB;
@@ -1193,15 +1296,11 @@ __global__ __launch_bounds__(NT) void wide_bwd(int s, double* __restrict__ zx, i
     const int j = threadIdx.x % 64, q = threadIdx.x / 64;
     const bool colok = j < kb;
     const double* Lc = fronts + foff[s] + (int64_t)m * (c0 + (colok ? j : 0));  // column c0 + j
-    // own diagonal block (column j in registers of wave 0) and reciprocal pivot
-    double a[SB];
-    double rinv = 1.0;
+    // column j of the inverse of the own diagonal block (wave 0; zero above the diagonal of the inverse)
+    double v[SB];
+    const double* Vj = winv + (int64_t)b * SB * SB + (int64_t)SB * j;  // Vj[t] = inv(L_bb)(t, j)
 #pragma unroll
-    for (int t = 0; t < SB; t++) a[t] = (q == 0 && colok && t > j && t < kb) ? Lc[c0 + t] : 0.0;
-    if (q == 0 && colok) rinv = 1.0 / Lc[c0 + j];
-    // the column scaled by its reciprocal pivot (see the forward sweep)
-#pragma unroll
-    for (int t = 0; t < SB; t++) a[t] *= rinv;
+    for (int t = 0; t < SB; t++) v[t] = (q == 0 && t >= j) ? Vj[t] : 0.0;
     const double t0 = (q == 0 && colok) ? y[f + c0 + j] : 0.0;  // this block's forward solution, also early
     double acc = 0.0;
     for (int r0 = nn; r0 < m; r0 += SB) {
@@ -1235,10 +1334,17 @@ __global__ __launch_bounds__(NT) void wide_bwd(int s, double* __restrict__ zx, i
     __syncthreads();
     if (q != 0) return;
     double tj = colok ? t0 - ((red[0][j] + red[1][j]) + (red[2][j] + red[3][j])) : 0.0;
-    double u = tj * rinv;
+    // x_b = inv(L_bb)^T t_b
+    tsh[j] = tj;  // read back by the other lanes of this wave
+    double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
 #pragma unroll
-    for (int t = SB - 1; t >= 0; t--)
-        if (t < kb) u = fma(-a[t], lane_value(u, t), u);
+    for (int t = 0; t < SB; t += 4) {
+        p0 = fma(v[t], tsh[t], p0);
+        p1 = fma(v[t + 1], tsh[t + 1], p1);
+        p2 = fma(v[t + 2], tsh[t + 2], p2);
+        p3 = fma(v[t + 3], tsh[t + 3], p3);
+    }
+    const double u = (p0 + p1) + (p2 + p3);
     store_coherent(zx + SB * b + j, colok ? u : 0.0);
     if (colok) y[f + c0 + j] = u;
 }
@@ -1673,6 +1779,18 @@ static void build_numeric_plan(chol_sym* C, const std::vector<int32_t>& colptr, 
             nflags += (C->h_ncol[s] + SB - 1) / SB;
         }
     C->dev.alloc(C->zx, std::max<int64_t>(nflags, 1) * SB);
+    // the wide fronts' diagonal-block inverses, refreshed by every factorization for the sweeps
+    std::vector<int32_t> wit;
+    for (int s = 0; s < ns; s++)
+        if (C->h_flag_off[s] >= 0)
+            for (int g = 0; g < (C->h_ncol[s] + SB - 1) / SB; g++) {
+                wit.push_back(s);
+                wit.push_back(g);
+                wit.push_back((int32_t)(C->h_flag_off[s] + g));
+            }
+    C->nwinv = (int)wit.size() / 3;
+    C->dev.alloc(C->winv, std::max<int64_t>(nflags, 1) * SB * SB);
+    C->dev.upload(C->winv_it, wit.empty() ? std::vector<int32_t>(3, 0) : wit);
     C->dev.upload(C->sfault, std::vector<int32_t>(1, 0));
     C->dev.upload(C->level_d, C->h_level);
     C->dev.alloc(C->statwords, 1);
@@ -1951,6 +2069,11 @@ void chol_factor_enqueue(chol_sym* C, const double* kval, hipStream_t st, double
             }
         }
     }
+    if (C->nwinv > 0) {  // diagonal-block inverses of the wide fronts for the sweeps
+        hipLaunchKernelGGL(wide_inverse, dim3(C->nwinv), dim3(64), 0, st, C->winv_it.p, C->ncol.p, C->mrows.p,
+                           C->foff.p, C->fronts.p, C->winv.p);
+        OPF_LAUNCH_CHECK();
+    }
 }
 
 __global__ void init_status(int ns, const int32_t* __restrict__ mrows, int32_t* __restrict__ status) {
@@ -2050,7 +2173,8 @@ static void solve_enqueue(chol_sym* C, const double* b, double* x, hipStream_t s
                 hipLaunchKernelGGL(fill_sentinel, dim3(ceil_div(nz, 256)), dim3(256), 0, st, nz, zx);
                 OPF_LAUNCH_CHECK();
                 hipLaunchKernelGGL(wide_fwd, dim3(g), dim3(NT), 0, st, s, zx, B.fault, C->first.p, C->ncol.p,
-                                   C->mrows.p, C->foff.p, C->roff.p, C->uoff.p, C->fronts.p, B.work, B.upd, y);
+                                   C->mrows.p, C->foff.p, C->roff.p, C->uoff.p, C->fronts.p, B.work, B.upd, y,
+                                   C->winv.p + C->h_flag_off[s] * SB * SB);
                 OPF_LAUNCH_CHECK();
             }
         }
@@ -2065,7 +2189,8 @@ static void solve_enqueue(chol_sym* C, const double* b, double* x, hipStream_t s
             hipLaunchKernelGGL(fill_sentinel, dim3(ceil_div(nz, 256)), dim3(256), 0, st, nz, zx);
             OPF_LAUNCH_CHECK();
             hipLaunchKernelGGL(wide_bwd, dim3((nn + SB - 1) / SB), dim3(NT), 0, st, s, zx, B.fault, C->first.p,
-                               C->ncol.p, C->mrows.p, C->foff.p, C->roff.p, C->rows.p, C->fronts.p, y);
+                               C->ncol.p, C->mrows.p, C->foff.p, C->roff.p, C->rows.p, C->fronts.p, y,
+                               C->winv.p + C->h_flag_off[s] * SB * SB);
             OPF_LAUNCH_CHECK();
         }
         int q0 = C->lvl_narrow_ptr[l], q1 = C->lvl_narrow_ptr[l + 1];
