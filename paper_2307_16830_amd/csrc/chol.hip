@@ -73,6 +73,8 @@ struct chol_sym {
     DBuf<int32_t> rows;
     DBuf<int32_t> child_ptr, child;
     DBuf<int64_t> rel_off;
+    DBuf<int64_t> gptr, gsrc;  // per front row (roff order): its children's update entries (indices into upd),
+                               // children in ascending order
     DBuf<int32_t> rel;
     DBuf<int32_t> tile_sn, tile_rc;  // tile work list: supernode, (tr << 16) | tc
     DBuf<int64_t> tile_cptr;         // per tile: its child rectangles in tile_crec
@@ -923,6 +925,22 @@ __global__ void permute_out(int n, const int32_t* __restrict__ perm, const doubl
 }
 
 constexpr int WIDE = 256;  // fronts with at least this many pivots use the sync-free solves
+
+// acc + the update entries gsrc[k0..k1) of one front row, added in list order, four loads in flight
+__device__ __forceinline__ double row_gather(double acc, int64_t k0, int64_t k1, const int64_t* __restrict__ gsrc,
+                                             const double* __restrict__ upd) {
+    int64_t k = k0;
+    for (; k + 3 < k1; k += 4) {
+        const int64_t s0 = gsrc[k], s1 = gsrc[k + 1], s2 = gsrc[k + 2], s3 = gsrc[k + 3];
+        const double u0 = upd[s0], u1 = upd[s1], u2 = upd[s2], u3 = upd[s3];
+        acc += u0;
+        acc += u1;
+        acc += u2;
+        acc += u3;
+    }
+    for (; k < k1; k++) acc += upd[gsrc[k]];
+    return acc;
+}
 constexpr int SCB = 16;    // pivot columns per block of the narrow-front sweeps
 
 // Forward sweep for one front: w = b(own rows) + children's partial results; solve with the diagonal
@@ -932,35 +950,19 @@ constexpr int SCB = 16;    // pivot columns per block of the narrow-front sweeps
 __global__ __launch_bounds__(NT) void solve_fwd(const int32_t* __restrict__ list, const int32_t* __restrict__ first,
                                                 const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
                                                 const int64_t* __restrict__ foff, const int64_t* __restrict__ roff,
-                                                const int64_t* __restrict__ uoff,
-                                                const int32_t* __restrict__ child_ptr,
-                                                const int32_t* __restrict__ child,
-                                                const int64_t* __restrict__ rel_off, const int32_t* __restrict__ rel,
+                                                const int64_t* __restrict__ uoff, const int64_t* __restrict__ gptr,
+                                                const int64_t* __restrict__ gsrc,
                                                 const double* __restrict__ fronts, double* __restrict__ work,
                                                 double* __restrict__ upd, double* __restrict__ y, int wcap) {
     extern __shared__ double wl[];
     const int s = list[blockIdx.x];
     const int m = mrows[s], nn = ncol[s], f = first[s];
     double* w = m <= wcap ? wl : work + roff[s];
-    for (int t = threadIdx.x; t < m; t += NT) w[t] = t < nn ? y[f + t] : 0.0;
+    // own right-hand side plus the children's update entries, each row summing its own list (children in
+    // ascending order), so no barrier per child
+    const int64_t* gp = gptr + roff[s];
+    for (int t = threadIdx.x; t < m; t += NT) w[t] = row_gather(t < nn ? y[f + t] : 0.0, gp[t], gp[t + 1], gsrc, upd);
     __syncthreads();
-    for (int ci = child_ptr[s]; ci < child_ptr[s + 1]; ci++) {
-        const int c = child[ci];
-        const int nu = mrows[c] - ncol[c];
-        const int32_t* rl = rel + rel_off[c];
-        const double* uc = upd + uoff[c];
-        int t = threadIdx.x;
-        for (; t + 3 * NT < nu; t += 4 * NT) {
-            const int r0 = rl[t], r1 = rl[t + NT], r2 = rl[t + 2 * NT], r3 = rl[t + 3 * NT];
-            const double u0 = uc[t], u1 = uc[t + NT], u2 = uc[t + 2 * NT], u3 = uc[t + 3 * NT];
-            w[r0] += u0;
-            w[r1] += u1;
-            w[r2] += u2;
-            w[r3] += u3;
-        }
-        for (; t < nu; t += NT) w[rl[t]] += uc[t];
-        __syncthreads();
-    }
     // blocks of SCB pivot columns: wave 0 solves the diagonal block in registers (solved values to zz), then
     // every thread applies the block's columns to its rows below it, all SCB loads of a row in flight at once.
     // Each w[i] takes the columns in increasing order, one fused multiply-add each, as a column-by-column
@@ -1119,28 +1121,18 @@ __device__ __forceinline__ double load_coherent(const double* p) {
         reinterpret_cast<unsigned long long*>(const_cast<double*>(p)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
 }
 
-// forward, step 0: w = [y(own rows), 0] + children's partial results (one work-group per front)
-__global__ __launch_bounds__(NT) void sfwd_gather(const int32_t* __restrict__ list, const int32_t* __restrict__ first,
+// forward, step 0 of a wide front: w = [y(own rows), 0] + the children's update entries, one thread per row
+// (children in ascending order), the rows spread over work-groups
+__global__ __launch_bounds__(NT) void sfwd_gather(int s, const int32_t* __restrict__ first,
                                                   const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
-                                                  const int64_t* __restrict__ roff, const int64_t* __restrict__ uoff,
-                                                  const int32_t* __restrict__ child_ptr,
-                                                  const int32_t* __restrict__ child,
-                                                  const int64_t* __restrict__ rel_off, const int32_t* __restrict__ rel,
-                                                  double* __restrict__ work, const double* __restrict__ upd,
-                                                  const double* __restrict__ y) {
-    const int s = list[blockIdx.x];
+                                                  const int64_t* __restrict__ roff, const int64_t* __restrict__ gptr,
+                                                  const int64_t* __restrict__ gsrc, double* __restrict__ work,
+                                                  const double* __restrict__ upd, const double* __restrict__ y) {
     const int m = mrows[s], nn = ncol[s], f = first[s];
-    double* w = work + roff[s];
-    for (int t = threadIdx.x; t < m; t += NT) w[t] = t < nn ? y[f + t] : 0.0;
-    __syncthreads();
-    for (int ci = child_ptr[s]; ci < child_ptr[s + 1]; ci++) {
-        const int c = child[ci];
-        const int nu = mrows[c] - ncol[c];
-        const int32_t* rl = rel + rel_off[c];
-        const double* uc = upd + uoff[c];
-        for (int t = threadIdx.x; t < nu; t += NT) w[rl[t]] += uc[t];
-        __syncthreads();
-    }
+    const int t = blockIdx.x * NT + threadIdx.x;
+    if (t >= m) return;
+    const int64_t* gp = gptr + roff[s];
+    work[roff[s] + t] = row_gather(t < nn ? y[f + t] : 0.0, gp[t], gp[t + 1], gsrc, upd);
 }
 
 // Solved blocks travel through an exchange buffer zx (64 doubles per pivot block) that is filled with the
@@ -1180,7 +1172,7 @@ __global__ __launch_bounds__(64) void wide_inverse(const int32_t* __restrict__ i
                                                    const int32_t* __restrict__ mrows,
                                                    const int64_t* __restrict__ foff, const double* __restrict__ fronts,
                                                    double* __restrict__ winv) {
-    __shared__ double Ls[SB * SB];  // Ls[k * 64 + i] = L(i, k) of the block
+    __shared__ __attribute__((aligned(16))) double Ls[SB * SB];  // Ls[i * 64 + k] = L(i, k) of the block
     __shared__ double ri[SB];
     const int s = items[3 * blockIdx.x], g = items[3 * blockIdx.x + 1];
     const int64_t ob = items[3 * blockIdx.x + 2];
@@ -1189,17 +1181,23 @@ __global__ __launch_bounds__(64) void wide_inverse(const int32_t* __restrict__ i
     const double* L = fronts + foff[s] + r0 + (int64_t)m * r0;
     const int j = threadIdx.x;
     for (int k = 0; k < SB; k++)
-        Ls[k * SB + j] = (j < nb && k < nb) ? (j >= k ? L[j + (int64_t)m * k] : 0.0) : (j == k ? 1.0 : 0.0);
+        Ls[j * SB + k] = (j < nb && k < nb) ? (j >= k ? L[j + (int64_t)m * k] : 0.0) : (j == k ? 1.0 : 0.0);
     __syncthreads();
     ri[j] = 1.0 / Ls[j * SB + j];
     __syncthreads();
+    // row i of L is contiguous in LDS (pairs of broadcasts per read); two partial sums per row
     double x[SB];
 #pragma unroll
     for (int i = 0; i < SB; i++) {
-        double acc = i == j ? 1.0 : 0.0;
+        double a0 = i == j ? 1.0 : 0.0, a1 = 0.0;
 #pragma unroll
-        for (int k = 0; k < i; k++) acc = fma(-Ls[k * SB + i], x[k], acc);
-        x[i] = acc * ri[i];
+        for (int k = 0; k + 1 < i; k += 2) {
+            const double2 l = *reinterpret_cast<const double2*>(&Ls[i * SB + k]);
+            a0 = fma(-l.x, x[k], a0);
+            a1 = fma(-l.y, x[k + 1], a1);
+        }
+        if (i % 2 == 1) a0 = fma(-Ls[i * SB + i - 1], x[i - 1], a0);
+        x[i] = (a0 + a1) * ri[i];
     }
     double* out = winv + ob * SB * SB + (int64_t)SB * j;  // column j
 #pragma unroll
@@ -1749,6 +1747,28 @@ static void build_numeric_plan(chol_sym* C, const std::vector<int32_t>& colptr, 
     C->dev.upload(C->child, clist);
     C->dev.upload(C->rel_off, reloff);
     C->dev.upload(C->rel, rel);
+    {
+        // extend-add of the solves in gather form: every front row lists the update entries that land on it
+        const int64_t nrows = C->h_roff[ns];
+        std::vector<int64_t> gp(nrows + 1, 0), gs;
+        for (int sn = 0; sn < ns; sn++)
+            for (int ci = cptr[sn]; ci < cptr[sn + 1]; ci++) {
+                const int c = clist[ci];
+                const int nu = C->h_mrows[c] - C->h_ncol[c];
+                for (int t = 0; t < nu; t++) gp[C->h_roff[sn] + rel[reloff[c] + t] + 1]++;
+            }
+        for (int64_t r = 0; r < nrows; r++) gp[r + 1] += gp[r];
+        gs.resize(gp[nrows]);
+        std::vector<int64_t> fill(gp.begin(), gp.end() - 1);
+        for (int sn = 0; sn < ns; sn++)
+            for (int ci = cptr[sn]; ci < cptr[sn + 1]; ci++) {
+                const int c = clist[ci];
+                const int nu = C->h_mrows[c] - C->h_ncol[c];
+                for (int t = 0; t < nu; t++) gs[fill[C->h_roff[sn] + rel[reloff[c] + t]]++] = C->h_uoff[c] + t;
+            }
+        C->dev.upload(C->gptr, gp);
+        C->dev.upload(C->gsrc, gs.empty() ? std::vector<int64_t>(1, 0) : gs);
+    }
     C->dev.upload(C->tile_sn, tsn);
     C->dev.upload(C->tile_cptr, tcptr);
     C->dev.upload(C->tile_crec, tcrec);
@@ -2154,19 +2174,17 @@ static void solve_enqueue(chol_sym* C, const double* b, double* x, hipStream_t s
             const int wcap = std::min(C->lvl_narrow_maxm[l], WLDS);  // fronts up to wcap rows keep w in LDS
             hipLaunchKernelGGL(solve_fwd, dim3(q1 - q0), dim3(NT), (size_t)wcap * sizeof(double), st,
                                C->lvl_narrow_d.p + q0, C->first.p, C->ncol.p, C->mrows.p, C->foff.p, C->roff.p,
-                               C->uoff.p, C->child_ptr.p, C->child.p, C->rel_off.p, C->rel.p, C->fronts.p,
-                               B.work, B.upd, y, wcap);
+                               C->uoff.p, C->gptr.p, C->gsrc.p, C->fronts.p, B.work, B.upd, y, wcap);
             OPF_LAUNCH_CHECK();
         }
         int w0 = C->lvl_wide_ptr[l], w1 = C->lvl_wide_ptr[l + 1];
         if (w1 > w0) {
-            hipLaunchKernelGGL(sfwd_gather, dim3(w1 - w0), dim3(NT), 0, st, C->lvl_wide_d.p + w0, C->first.p,
-                               C->ncol.p, C->mrows.p, C->roff.p, C->uoff.p, C->child_ptr.p, C->child.p, C->rel_off.p,
-                               C->rel.p, B.work, B.upd, y);
-            OPF_LAUNCH_CHECK();
             for (int q = w0; q < w1; q++) {
                 const int s = C->lvl_wide[q];
                 const int m = C->h_mrows[s], nn = C->h_ncol[s];
+                hipLaunchKernelGGL(sfwd_gather, dim3(ceil_div(m, NT)), dim3(NT), 0, st, s, C->first.p, C->ncol.p,
+                                   C->mrows.p, C->roff.p, C->gptr.p, C->gsrc.p, B.work, B.upd, y);
+                OPF_LAUNCH_CHECK();
                 const int g = (nn + SB - 1) / SB + (m - nn + SB - 1) / SB;
                 double* zx = B.zx + C->h_flag_off[s] * SB;
                 const int64_t nz = (int64_t)((nn + SB - 1) / SB) * SB;
