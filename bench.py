@@ -395,7 +395,8 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved_tflops, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tflops / PEAK_FP64_TFLOPS, "traffic": recorded_traffic(args.config, kname),
                      "kernel": kname, "avg_launch_ms": avg_ms, "launches": kt["launches"],
-                     "flops_per_launch": flops_per_launch, "timing": where,
+                     "flops_per_launch": flops_per_launch,
+                     "algorithmic_bytes_per_launch": kt["bytes"] / max(kt["launches"], 1), "timing": where,
                      "trailing_update": {"launches": kt_tu["launches"], "avg_launch_ms": tu_avg,
                                          "tflops": (kt_tu["flops"] / max(kt_tu["launches"], 1)) / (tu_avg * 1e-3)
                                          / 1e12 if tu_avg > 0 else None}},
