@@ -21,11 +21,11 @@ def opf():
     return _opf
 
 
-def trace_grids(count, nmax):
-    """The first ``count`` requests of the serving trace with at most ``nmax`` buses."""
+def trace_grids(count, nmax, nmin=0):
+    """The first ``count`` requests of the serving trace with ``nmin`` to ``nmax`` buses."""
     out = []
     for seed, nb, ne, ng, lf in gridgen.serving_trace(512):
-        if nb <= nmax:
+        if nmin <= nb <= nmax:
             out.append((seed, gridgen.make_grid(nb, ne, ng, seed, load_factor=lf)))
         if len(out) == count:
             break
@@ -70,6 +70,25 @@ def test_results_equal_alone_and_in_the_mix():
         assert r["t_submit"] <= r["t_admit"] <= r["t_done"]
         assert r["footprint"] > 0
     assert st["in_use"] == 0 and st["running"] == 0 and st["queued"] == 0
+    srv.close()
+
+
+def test_large_requests_equal_alone_and_in_the_mix():
+    """Requests from 1,000 to 2,000 buses (blocked fronts, wide-front sweeps, graph replay) mixed with small ones:
+    each request's result in the mix is bitwise the one it gets alone."""
+    grids = trace_grids(4, 2000, 1000) + trace_grids(4, 300)
+    alone = {tag: solve_alone(g) for tag, g in grids}
+    srv = opf().Server(slots=4, hbm_budget=4 << 30)
+    for tag, g in grids:
+        srv.submit(g, tag)
+    res = drain(srv, len(grids))
+    for tag, g in grids:
+        r = res[tag]
+        s0, it0, obj0, x0 = alone[tag]
+        assert r["status"] == s0, (tag, r["status"], s0, r["message"])
+        assert r["iterations"] == it0, (tag, r["iterations"], it0)
+        x = srv.x(tag, r["n"])
+        assert np.array_equal(x, x0), tag
     srv.close()
 
 
