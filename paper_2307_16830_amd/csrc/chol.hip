@@ -53,6 +53,9 @@ struct chol_sym {
     std::vector<int32_t> lvl_small_ptr, lvl_small;  // fronts with m <= 64 by level
     std::vector<int32_t> lvl_narrow_ptr, lvl_narrow;  // fronts solved by one work-group, by level
     std::vector<int32_t> lvl_narrow_maxm;             // largest front of each level's list
+    // narrow fronts with many rows below their pivots ("tall"): the sweeps' products with those rows run as
+    // separate launches over row blocks (forward) and 16-column blocks (backward), items (front, block)
+    std::vector<int32_t> lvl_trow_ptr, lvl_tcol_ptr, trow_it, tcol_it;
     std::vector<int32_t> lvl_wide_ptr, lvl_wide;      // fronts with >= WIDE pivots, by level
     // assembly tile work list (per level)
     std::vector<int32_t> asm_ptr;                  // [nlevels+1] into tiles
@@ -82,6 +85,7 @@ struct chol_sym {
     DBuf<int64_t> tile_kptr;
     DBuf<int32_t> tile_k, tile_kpos;
     DBuf<int32_t> lvl_sn_d, lvl_small_d, lvl_narrow_d, lvl_wide_d;
+    DBuf<int32_t> trow_d, tcol_d;
     DBuf<int32_t> potrf_it, trsm_it, syrk_it;  // packed items
     DBuf<int32_t> next_slot;  // per trailing-update item: slot of the next panel's diagonal block, or -1
 
@@ -942,6 +946,7 @@ __device__ __forceinline__ double row_gather(double acc, int64_t k0, int64_t k1,
     return acc;
 }
 constexpr int SCB = 16;    // pivot columns per block of the narrow-front sweeps
+constexpr int TALL = 512;  // narrow fronts with at least this many rows below their pivots are "tall"
 
 // Forward sweep for one front: w = b(own rows) + children's partial results; solve with the diagonal
 // block; keep w on the off-diagonal rows as this front's partial result.  w lives in LDS (dynamic, wcap
@@ -961,7 +966,9 @@ __global__ __launch_bounds__(NT) void solve_fwd(const int32_t* __restrict__ list
     // own right-hand side plus the children's update entries, each row summing its own list (children in
     // ascending order), so no barrier per child
     const int64_t* gp = gptr + roff[s];
-    for (int t = threadIdx.x; t < m; t += NT) w[t] = row_gather(t < nn ? y[f + t] : 0.0, gp[t], gp[t + 1], gsrc, upd);
+    // a tall front's rows below its pivots are gathered and updated by solve_fwd_rows after this launch
+    const int mr = m - nn >= TALL ? nn : m;
+    for (int t = threadIdx.x; t < mr; t += NT) w[t] = row_gather(t < nn ? y[f + t] : 0.0, gp[t], gp[t + 1], gsrc, upd);
     __syncthreads();
     // blocks of SCB pivot columns: wave 0 solves the diagonal block in registers (solved values to zz), then
     // every thread applies the block's columns to its rows below it, all SCB loads of a row in flight at once.
@@ -987,7 +994,7 @@ __global__ __launch_bounds__(NT) void solve_fwd(const int32_t* __restrict__ list
             }
         }
         __syncthreads();
-        for (int i = j0 + cb + threadIdx.x; i < m; i += NT) {
+        for (int i = j0 + cb + threadIdx.x; i < mr; i += NT) {
             double lv[SCB];
 #pragma unroll
             for (int t = 0; t < SCB; t++) lv[t] = t < cb ? L[i + (int64_t)m * (j0 + t)] : 0.0;
@@ -999,12 +1006,45 @@ __global__ __launch_bounds__(NT) void solve_fwd(const int32_t* __restrict__ list
         }
         __syncthreads();
     }
-    for (int t = threadIdx.x; t < m; t += NT) {
+    for (int t = threadIdx.x; t < mr; t += NT) {
         if (t < nn)
             y[f + t] = zz[t];
         else
             upd[uoff[s] + (t - nn)] = w[t];
     }
+}
+
+// Rows below the pivots of a tall front, 256 rows per work-group (item: front, row block): the row's gathered
+// update entries, then the pivot columns in increasing order, one fused multiply-add each (the order of the
+// single-work-group sweep), 16 loads in flight; the result is the front's partial result for its parent.
+__global__ __launch_bounds__(NT) void solve_fwd_rows(const int32_t* __restrict__ items,
+                                                     const int32_t* __restrict__ first,
+                                                     const int32_t* __restrict__ ncol,
+                                                     const int32_t* __restrict__ mrows,
+                                                     const int64_t* __restrict__ foff, const int64_t* __restrict__ roff,
+                                                     const int64_t* __restrict__ uoff, const int64_t* __restrict__ gptr,
+                                                     const int64_t* __restrict__ gsrc,
+                                                     const double* __restrict__ fronts, double* __restrict__ upd,
+                                                     const double* __restrict__ y) {
+    __shared__ double zs[WIDE];
+    const int s = items[2 * blockIdx.x], rb = items[2 * blockIdx.x + 1];
+    const int m = mrows[s], nn = ncol[s], f = first[s];
+    for (int j = threadIdx.x; j < nn; j += NT) zs[j] = y[f + j];
+    __syncthreads();
+    const int i = nn + rb * NT + threadIdx.x;
+    if (i >= m) return;
+    const int64_t* gp = gptr + roff[s];
+    double acc = row_gather(0.0, gp[i], gp[i + 1], gsrc, upd);
+    const double* L = fronts + foff[s] + i;
+    for (int j0 = 0; j0 < nn; j0 += SCB) {
+        double lv[SCB];
+#pragma unroll
+        for (int t = 0; t < SCB; t++) lv[t] = j0 + t < nn ? L[(int64_t)m * (j0 + t)] : 0.0;
+#pragma unroll
+        for (int t = 0; t < SCB; t++)
+            if (j0 + t < nn) acc = fma(-lv[t], zs[j0 + t], acc);
+    }
+    upd[uoff[s] + (i - nn)] = acc;
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -1029,8 +1069,11 @@ __global__ __launch_bounds__(NT) void solve_bwd(const int32_t* __restrict__ list
     const double* L = fronts + foff[s];
     double* w = work + roff[s];
     const int wv = threadIdx.x / 64, ln = threadIdx.x % 64;
-    for (int j = threadIdx.x; j < nn; j += NT) w[j] = y[f + j];
-    for (int r0 = nn; r0 < m; r0 += XCH) {
+    // a tall front's products with the rows below were formed by solve_bwd_dots (w of its pivots in work)
+    const bool tall = m - nn >= TALL;
+    if (!tall)
+        for (int j = threadIdx.x; j < nn; j += NT) w[j] = y[f + j];
+    for (int r0 = nn; r0 < (tall ? nn : m); r0 += XCH) {
         const int nr = min(XCH, m - r0);
         __syncthreads();
         int t = threadIdx.x;
@@ -1096,6 +1139,95 @@ __global__ __launch_bounds__(NT) void solve_bwd(const int32_t* __restrict__ list
         __syncthreads();
     }
     for (int j = threadIdx.x; j < nn; j += NT) y[f + j] = xx[j];
+}
+
+// Products of a tall front's pivot columns with the solved values at its rows below, 16 columns per work-group
+// (item: front, column block): w_j = y_j - L21(:, j)^T x(rows below) for its columns, written to the front's
+// slice of work for solve_bwd.  The solved values are staged into LDS up to XBT rows at a time (eight row
+// indices, then eight values, in flight per thread); each wave forms four columns' products side by side,
+// four partial sums each, combined in a fixed order.
+constexpr int XBT = 8192;  // rows of solved values staged per pass (64 KB)
+__global__ __launch_bounds__(NT) void solve_bwd_dots(const int32_t* __restrict__ items,
+                                                     const int32_t* __restrict__ first,
+                                                     const int32_t* __restrict__ ncol,
+                                                     const int32_t* __restrict__ mrows,
+                                                     const int64_t* __restrict__ foff, const int64_t* __restrict__ roff,
+                                                     const int32_t* __restrict__ rows,
+                                                     const double* __restrict__ fronts, double* __restrict__ work,
+                                                     const double* __restrict__ y) {
+    __shared__ double xb[XBT];
+    const int s = items[2 * blockIdx.x], cb = items[2 * blockIdx.x + 1];
+    const int m = mrows[s], nn = ncol[s], f = first[s];
+    const int32_t* R = rows + roff[s];
+    const double* L = fronts + foff[s];
+    const int wv = threadIdx.x / 64, ln = threadIdx.x % 64;
+    constexpr int KW = SCB / 4;
+    double wj[KW];
+    bool on[KW];
+#pragma unroll
+    for (int k = 0; k < KW; k++) {
+        const int j = SCB * cb + wv + 4 * k;
+        on[k] = j < nn;
+        wj[k] = on[k] ? y[f + j] : 0.0;
+    }
+    for (int r0 = nn; r0 < m; r0 += XBT) {
+        const int nr = min(XBT, m - r0);
+        __syncthreads();
+        for (int t0 = threadIdx.x; t0 < nr; t0 += 8 * NT) {
+            int ri[8];
+#pragma unroll
+            for (int q = 0; q < 8; q++) ri[q] = t0 + q * NT < nr ? R[r0 + t0 + q * NT] : -1;
+#pragma unroll
+            for (int q = 0; q < 8; q++)
+                if (ri[q] >= 0) xb[t0 + q * NT] = y[ri[q]];
+        }
+        __syncthreads();
+        const double* col[KW];
+        double a[KW][4];
+#pragma unroll
+        for (int k = 0; k < KW; k++) {
+            col[k] = L + (int64_t)m * (on[k] ? SCB * cb + wv + 4 * k : 0) + r0;
+            a[k][0] = a[k][1] = a[k][2] = a[k][3] = 0.0;
+        }
+        int t = ln;
+        // two steps' loads (32 per lane) issued before their multiply-adds
+        for (; t + 448 < nr; t += 512) {
+            double v[2][KW][4];
+#pragma unroll
+            for (int h = 0; h < 2; h++)
+#pragma unroll
+                for (int k = 0; k < KW; k++)
+#pragma unroll
+                    for (int p = 0; p < 4; p++) v[h][k][p] = on[k] ? col[k][t + 256 * h + 64 * p] : 0.0;
+#pragma unroll
+            for (int h = 0; h < 2; h++)
+#pragma unroll
+                for (int k = 0; k < KW; k++)
+#pragma unroll
+                    for (int p = 0; p < 4; p++) a[k][p] += v[h][k][p] * xb[t + 256 * h + 64 * p];
+        }
+        for (; t + 192 < nr; t += 256) {
+#pragma unroll
+            for (int k = 0; k < KW; k++)
+                if (on[k]) {
+                    a[k][0] += col[k][t] * xb[t];
+                    a[k][1] += col[k][t + 64] * xb[t + 64];
+                    a[k][2] += col[k][t + 128] * xb[t + 128];
+                    a[k][3] += col[k][t + 192] * xb[t + 192];
+                }
+        }
+        for (; t < nr; t += 64)
+#pragma unroll
+            for (int k = 0; k < KW; k++)
+                if (on[k]) a[k][0] += col[k][t] * xb[t];
+#pragma unroll
+        for (int k = 0; k < KW; k++)
+            if (on[k]) wj[k] -= wave_sum((a[k][0] + a[k][1]) + (a[k][2] + a[k][3]));
+    }
+    if (ln == 0)
+#pragma unroll
+        for (int k = 0; k < KW; k++)
+            if (on[k]) work[roff[s] + SCB * cb + wv + 4 * k] = wj[k];
 }
 
 // ---------------------------------------------------------------- sync-free solves for wide fronts
@@ -1451,6 +1583,26 @@ static void build_numeric_plan(chol_sym* C, const std::vector<int32_t>& colptr, 
         C->lvl_narrow_maxm.push_back(mx);
         C->lvl_wide_ptr[l + 1] = (int32_t)C->lvl_wide.size();
     }
+    C->lvl_trow_ptr.assign(nl + 1, 0);
+    C->lvl_tcol_ptr.assign(nl + 1, 0);
+    C->trow_it.clear();
+    C->tcol_it.clear();
+    for (int l = 0; l < nl; l++) {
+        for (int q = C->lvl_narrow_ptr[l]; q < C->lvl_narrow_ptr[l + 1]; q++) {
+            const int s = C->lvl_narrow[q], m = C->h_mrows[s], nn = C->h_ncol[s];
+            if (m - nn < TALL) continue;
+            for (int rb = 0; rb * NT < m - nn; rb++) {
+                C->trow_it.push_back(s);
+                C->trow_it.push_back(rb);
+            }
+            for (int cb = 0; cb * SCB < nn; cb++) {
+                C->tcol_it.push_back(s);
+                C->tcol_it.push_back(cb);
+            }
+        }
+        C->lvl_trow_ptr[l + 1] = (int32_t)C->trow_it.size() / 2;
+        C->lvl_tcol_ptr[l + 1] = (int32_t)C->tcol_it.size() / 2;
+    }
     // assembly tiles and K entries per tile
     std::vector<int32_t> tsn, trc;
     C->asm_ptr.assign(nl + 1, 0);
@@ -1779,6 +1931,8 @@ static void build_numeric_plan(chol_sym* C, const std::vector<int32_t>& colptr, 
     C->dev.upload(C->lvl_sn_d, C->lvl_sn);
     C->dev.upload(C->lvl_small_d, C->lvl_small);
     C->dev.upload(C->lvl_narrow_d, C->lvl_narrow);
+    C->dev.upload(C->trow_d, C->trow_it.empty() ? std::vector<int32_t>(2, 0) : C->trow_it);
+    C->dev.upload(C->tcol_d, C->tcol_it.empty() ? std::vector<int32_t>(2, 0) : C->tcol_it);
     C->dev.upload(C->lvl_wide_d, C->lvl_wide);
     C->dev.upload(C->potrf_it, pot);
     C->dev.upload(C->trsm_it, trs);
@@ -2176,6 +2330,13 @@ static void solve_enqueue(chol_sym* C, const double* b, double* x, hipStream_t s
                                C->lvl_narrow_d.p + q0, C->first.p, C->ncol.p, C->mrows.p, C->foff.p, C->roff.p,
                                C->uoff.p, C->gptr.p, C->gsrc.p, C->fronts.p, B.work, B.upd, y, wcap);
             OPF_LAUNCH_CHECK();
+            const int t0 = C->lvl_trow_ptr[l], t1 = C->lvl_trow_ptr[l + 1];
+            if (t1 > t0) {  // the tall fronts' rows below their pivots
+                hipLaunchKernelGGL(solve_fwd_rows, dim3(t1 - t0), dim3(NT), 0, st, C->trow_d.p + 2 * t0, C->first.p,
+                                   C->ncol.p, C->mrows.p, C->foff.p, C->roff.p, C->uoff.p, C->gptr.p, C->gsrc.p,
+                                   C->fronts.p, B.upd, y);
+                OPF_LAUNCH_CHECK();
+            }
         }
         int w0 = C->lvl_wide_ptr[l], w1 = C->lvl_wide_ptr[l + 1];
         if (w1 > w0) {
@@ -2212,6 +2373,12 @@ static void solve_enqueue(chol_sym* C, const double* b, double* x, hipStream_t s
             OPF_LAUNCH_CHECK();
         }
         int q0 = C->lvl_narrow_ptr[l], q1 = C->lvl_narrow_ptr[l + 1];
+        const int c0 = C->lvl_tcol_ptr[l], c1 = C->lvl_tcol_ptr[l + 1];
+        if (c1 > c0) {  // the tall fronts' products with their rows below
+            hipLaunchKernelGGL(solve_bwd_dots, dim3(c1 - c0), dim3(NT), 0, st, C->tcol_d.p + 2 * c0, C->first.p,
+                               C->ncol.p, C->mrows.p, C->foff.p, C->roff.p, C->rows.p, C->fronts.p, B.work, y);
+            OPF_LAUNCH_CHECK();
+        }
         if (q1 > q0) {
             hipLaunchKernelGGL(solve_bwd, dim3(q1 - q0), dim3(NT), 0, st, C->lvl_narrow_d.p + q0, C->first.p,
                                C->ncol.p, C->mrows.p, C->foff.p, C->roff.p, C->rows.p, C->fronts.p, B.work, y);
