@@ -174,6 +174,10 @@ typedef struct {
      * as one rank-128 update (half the passes over the trailing matrix);
      * default 2048, 0: never */
     int32_t pair_min;
+    /* panels per group when pairing (2..8, default 2): the group's last
+     * step applies all of them to the rest of the front as one update of
+     * rank 64 * pair_panels */
+    int32_t pair_panels;
 } chol_options;
 
 typedef struct chol_sym chol_sym;

@@ -1776,15 +1776,22 @@ static void build_numeric_plan(chol_sym* C, const std::vector<int32_t>& colptr, 
         const bool paired = nblocked == 1 && C->opts.pair_min > 0 && C->h_ncol[only] >= C->opts.pair_min;
         // pairs cover the leading steps whose pair still leaves at least pair_min rows below it (where the
         // update is bound by passes over a large trailing matrix); the later, latency-bound steps are single
+        // groups of G = pair_panels panels (2: pairs); within a group, every step but the last updates only the
+        // group's next panel, the last applies the whole group to the rest of the front (rank 64 G)
+        const int G = std::max(2, std::min(C->opts.pair_panels, 8));
         int npair_steps = 0;
         if (paired) {
             const int nn = C->h_ncol[only], m = C->h_mrows[only];
-            while ((npair_steps + 2) * TB < nn && m - (npair_steps + 2) * TB >= C->opts.pair_min) npair_steps += 2;
+            while ((npair_steps + G) * TB < nn && m - (npair_steps + G) * TB >= C->opts.pair_min) npair_steps += G;
         }
         for (int k = 0; k < maxsteps; k++) {
-            // pairing: step kind 1 = first panel of a pair, 2 = second panel (rank-128 trailing update)
-            int kind = 0;
-            if (k < npair_steps) kind = k % 2 == 0 ? 1 : 2;
+            // step kind 1 = a panel of a group before its last, 2 = the group's last panel (rank-64 G update);
+            // gpos = position in the group
+            int kind = 0, gpos = 0;
+            if (k < npair_steps) {
+                gpos = k % G;
+                kind = gpos < G - 1 ? 1 : 2;
+            }
             chol_sym::Step st{l, (int32_t)pot.size() / 2, 0, (int32_t)trs.size() / 4, 0, 0, 0, 0, 0, TB};
             for (int q = C->lvl_ptr[l]; q < C->lvl_ptr[l + 1]; q++) {
                 int s = C->lvl_sn[q];
@@ -1810,14 +1817,14 @@ static void build_numeric_plan(chol_sym* C, const std::vector<int32_t>& colptr, 
             max_slots = std::max(max_slots, st.p1 - st.p0);
             // trailing update: the next panel's 64 columns (128 x 64 tiles), then the rest (128 x 128); the
             // items carry the first column of the panels applied, the step their total width
-            const int kfirst = kind == 2 ? (k - 1) * TB : k * TB;
-            if (kind == 2 && only >= 0) st.kw = std::min(k * TB + TB, C->h_ncol[only]) - kfirst;
+            const int kfirst = (k - gpos) * TB;  // first column of the group's panels applied by this step
+            if (kind != 0 && only >= 0) st.kw = std::min(k * TB + TB, C->h_ncol[only]) - kfirst;
             for (int pass = 0; pass < 2; pass++) {
                 if (pass == 0)
                     st.s0 = (int32_t)syr.size() / 4;
                 else
                     st.r0 = (int32_t)syr.size() / 4;
-                if (pass == 1 && kind == 1) {  // the first panel of a pair updates the second panel only
+                if (pass == 1 && kind == 1) {  // a panel before the group's last updates the next panel only
                     st.r1 = (int32_t)syr.size() / 4;
                     continue;
                 }
@@ -1861,11 +1868,11 @@ static void build_numeric_plan(chol_sym* C, const std::vector<int32_t>& colptr, 
                 if (m <= TB || C->is_dense[s] || k * TB >= nn) continue;
                 const double base = k * TB + std::min(TB, nn - k * TB), r = m - base;
                 if (kind == 1) {
-                    // rank-64 update of the next panel's columns below the diagonal
+                    // rank-kw update of the next panel's columns below the diagonal (kw = the group's panels so far)
                     const double w = std::min<double>(TB, r);
                     const double ent = w * r - w * (w - 1) / 2;
-                    fl += 2.0 * TB * ent;
-                    by += 16.0 * ent + 8.0 * TB * (r + w);
+                    fl += 2.0 * st.kw * ent;
+                    by += 16.0 * ent + 8.0 * st.kw * (r + w);
                 } else {
                     const double kw = kind == 2 ? st.kw : std::min(TB, nn - k * TB);
                     fl += r * (r + 1) * kw;  // symmetric rank-kw update of an r x r lower triangle
@@ -1979,6 +1986,7 @@ extern "C" void chol_default_options(chol_options* o) {
     o->pivot_tol = 0.0;
     o->tile_min = 0;
     o->pair_min = 2048;
+    o->pair_panels = 2;
 }
 
 extern "C" int chol_analyze(int32_t n, const int32_t* colptr, const int32_t* rowind, const chol_options* opts,

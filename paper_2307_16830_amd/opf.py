@@ -68,7 +68,7 @@ class IpmResult(ctypes.Structure):
 class CholOptions(ctypes.Structure):
     _fields_ = [("dense_frac", ctypes.c_double), ("dense_abs", ctypes.c_int32), ("max_width", ctypes.c_int32),
                 ("zero_abs", ctypes.c_int64), ("zero_rel", ctypes.c_double), ("pivot_tol", ctypes.c_double),
-                ("tile_min", ctypes.c_int32), ("pair_min", ctypes.c_int32)]
+                ("tile_min", ctypes.c_int32), ("pair_min", ctypes.c_int32), ("pair_panels", ctypes.c_int32)]
 
 
 class IpmOptions(ctypes.Structure):

@@ -326,6 +326,27 @@ def test_dense_front_blocked_cholesky(n):
     assert np.max(np.abs(L - Lref)) <= 1e-12 * np.max(np.abs(Lref))
 
 
+@pytest.mark.parametrize("n,g", [(900, 3), (1300, 4), (1300, 8)])
+def test_dense_front_panel_groups(n, g):
+    """Panels grouped g at a time (the group's earlier steps update only its next panel, its last step applies
+    all g panels to the rest of the front, rank 64 g) give the same factor as the textbook Cholesky."""
+    rng = np.random.default_rng(n + g)
+    A = rng.normal(size=(n, n))
+    K = A @ A.T + n * np.eye(n)
+    rows, cols = np.tril_indices(n)
+    cp, ri = ochol.lower_csc(n, rows, cols)
+    colidx = np.repeat(np.arange(n), np.diff(cp))
+    C = opf().Cholesky(n, cp, ri, opf().chol_options(pair_min=384, pair_panels=g))
+    assert C.factor(dev(K[ri, colidx])) == -1
+    lp, li, lx = C.export_factor()
+    perm = C.perm()
+    L = np.zeros((n, n))
+    for j in range(n):
+        L[li[lp[j]:lp[j + 1]], j] = lx[lp[j]:lp[j + 1]]
+    Lref = np.linalg.cholesky(K[np.ix_(perm, perm)])
+    assert np.max(np.abs(L - Lref)) <= 1e-12 * np.max(np.abs(Lref))
+
+
 def _block_system(a, b, c, seed):
     """SPD matrix of two cliques (a and b vertices) joined by a separator of c vertices adjacent to both:
     with dense-row detection off, each clique is a front with many pivots and c rows below them."""
