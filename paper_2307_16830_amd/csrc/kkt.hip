@@ -100,7 +100,8 @@ __global__ __launch_bounds__(KB) void seg_gather(int nwaves, const int32_t* __re
                                                  const uint64_t* __restrict__ term,
                                                  const uint64_t* __restrict__ smask,
                                                  const uint64_t* __restrict__ emask,
-                                                 const int32_t* __restrict__ base, Eval ev,
+                                                 const int32_t* __restrict__ base,
+                                                 const int32_t* __restrict__ segout, Eval ev,
                                                  const double* __restrict__ add, double* __restrict__ out) {
     const int w = blockIdx.x * (KB / 64) + threadIdx.x / 64;
     if (w >= nwaves) return;
@@ -122,14 +123,17 @@ __global__ __launch_bounds__(KB) void seg_gather(int nwaves, const int32_t* __re
             }
         }
         if ((em >> lane) & 1) {
-            const int o = base[c] + __popcll(sm & below & ~1ull);
+            const int so = base[c] + __popcll(sm & below & ~1ull);  // segment (output) ordinal
+            const int o = segout ? segout[so] : so;
             out[o] = add ? add[o] + v : v;
         }
         carry = __shfl(v, 63);
     }
 }
 
-// Build a SegList from (output, code) pairs already in output order.  Wave ranges are SEG_CPW chunks long and
+// Build a SegList from (output, code) pairs grouped by output (consecutive terms of one output form its segment).
+// Segments in increasing output order need no map; any other order (chosen for the locality of the terms' reads)
+// gets segout, the output of each segment.  Wave ranges are SEG_CPW chunks long and
 // begin at a chunk boundary: an output that would straddle a range boundary is moved to the next range, the
 // gap filled with `zero_code` terms (value 0, no start or end bit), so no output is split between waves
 // except one longer than a whole range, which extends its range.
@@ -138,7 +142,9 @@ void build_seglist(SegList& L, const std::vector<int32_t>& outs, const std::vect
     const int64_t n_in = (int64_t)codes.size();
     const int64_t RW = (int64_t)SEG_CPW * 64;  // terms per range
     std::vector<uint64_t> term;
-    std::vector<int32_t> tout;     // output of each placed term (-1 for padding)
+    std::vector<int32_t> tout;     // segment ordinal of each placed term (-1 for padding)
+    std::vector<int32_t> segs;     // output of each segment
+    bool ordered = true;
     std::vector<char> first, last;  // term starts / ends its output
     term.reserve(n_in + n_in / 8 + 64);
     for (int64_t t = 0; t < n_in;) {
@@ -152,12 +158,15 @@ void build_seglist(SegList& L, const std::vector<int32_t>& outs, const std::vect
                 first.push_back(0);
                 last.push_back(0);
             }
+        if (!segs.empty() && outs[t] != segs.back() + 1) ordered = false;
+        if (segs.empty() && outs[t] != 0) ordered = false;
         for (int64_t q = t; q < u; q++) {
             term.push_back(codes[q]);
-            tout.push_back(outs[q]);
+            tout.push_back((int32_t)segs.size());
             first.push_back(q == t);
             last.push_back(q == u - 1);
         }
+        segs.push_back(outs[t]);
         t = u;
     }
     const int64_t nt = (int64_t)term.size();
@@ -186,13 +195,14 @@ void build_seglist(SegList& L, const std::vector<int32_t>& outs, const std::vect
     dev.upload(L.emask, em);
     dev.upload(L.base, base);
     dev.upload(L.wptr, wptr);
+    if (!ordered) dev.upload(L.segout, segs);
 }
 
 template <class Eval>
 static void run_seg(const SegList& L, Eval ev, const double* add, double* out, hipStream_t s) {
     if (L.nwaves == 0) return;
     hipLaunchKernelGGL(seg_gather<Eval>, dim3(ceil_div(L.nwaves, KB / 64)), dim3(KB), 0, s, L.nwaves, L.wptr.p,
-                       L.term.p, L.smask.p, L.emask.p, L.base.p, ev, add, out);
+                       L.term.p, L.smask.p, L.emask.p, L.base.p, L.segout.p, ev, add, out);
     OPF_LAUNCH_CHECK();
 }
 
@@ -390,7 +400,19 @@ void build_kkt_maps(opf_model* M) {
         outs.clear();
         codes.clear();
         const int64_t nk = M->nnzk;
+        // K slots visited by the smallest constraint row among their Jacobian pair terms (ties by slot): the
+        // slots of one row are adjacent, and consecutive rows of a template family read neighbouring J, D and
+        // Hessian entries (the family-major layouts), instead of one random line per read
+        std::vector<int64_t> slot(nk);
+        std::vector<int32_t> key(nk);
         for (int64_t k = 0; k < nk; k++) {
+            slot[k] = k;
+            int32_t r = INT32_MAX;
+            for (int e = pptr[k]; e < pptr[k + 1]; e++) r = std::min(r, pr[e]);
+            key[k] = r;
+        }
+        std::stable_sort(slot.begin(), slot.end(), [&](int64_t a, int64_t b) { return key[a] < key[b]; });
+        for (int64_t k : slot) {
             if (kdiag[k] >= 0) {
                 outs.push_back((int32_t)k);
                 codes.push_back((uint64_t)kdiag[k] | (KT_DIAG << 44));

@@ -12,7 +12,8 @@ namespace opf {
 struct SegList {
     DBuf<uint64_t> term;          // [nchunks * 64]
     DBuf<uint64_t> smask, emask;  // [nchunks]: bit l set if term l is the first / last term of its output
-    DBuf<int32_t> base;           // [nchunks]: output index of the chunk's first term
+    DBuf<int32_t> base;           // [nchunks]: output (or, with segout, segment ordinal) of the chunk's first term
+    DBuf<int32_t> segout;         // [nsegments] output of each segment when segments are not in output order
     DBuf<int32_t> wptr;           // [nwaves + 1]: chunk range of each wave
     int nwaves = 0;
     int64_t nterms = 0;
