@@ -3,10 +3,12 @@
 // fixed pivot sequence because it is positive definite once the inertia is
 // right).
 //
-// Numeric layout: supernode s owns a dense column-major front F_s of m_s x m_s
-// doubles (m_s = number of rows of the supernode, its n_s own columns first).
-// After the partial factorization the first n_s columns hold L's panel and
-// the trailing (m_s - n_s) block holds the update matrix passed to the parent.
+// Numeric layout: supernode s owns a dense front F_s of m_s x m_s (m_s =
+// number of rows of the supernode, its n_s own columns first), of which only
+// the lower part is stored, as a block trapezoid of 64-column panels (fcol
+// below).  After the partial factorization the first n_s columns hold L's
+// panel and the trailing (m_s - n_s) block holds the update matrix passed to
+// the parent.
 // Fronts are processed by elimination-tree level (leaves first); all fronts
 // of a level are independent and run in the same launches:
 //   * assembly: one work-group per 64x64 lower tile of a front gathers the
@@ -28,6 +30,7 @@
 #include <climits>
 #include <cmath>
 #include <mutex>
+#include <type_traits>
 
 #include "model.h"
 #include "symbolic.h"
@@ -148,6 +151,24 @@ namespace {
 constexpr int TB = 64;      // tile edge
 constexpr int NT = 256;     // threads per work-group
 
+// Front storage.  The columns of an m-row front are cut into 64-column panels; panel p is a column-major
+// block of m - 64p rows starting at row 64p, and the panels follow one another.  Entry (r, c) with
+// r >= 64 floor(c / 64) (every lower entry; of the strictly upper part only the upper halves of the 64 x 64
+// diagonal blocks take memory, and they are never read) is at fcol(m, c) + r, and within a panel column
+// c + 1 follows column c at the panel's row count fld(m, c).  A front of at most 64 rows is a plain
+// column-major square.
+static_assert(TB == 64, "the front layout's panels are the 64-column blocks");
+__host__ __device__ __forceinline__ int64_t fcol(int64_t m, int c) {
+    const int64_t p = c >> 6;
+    return p * (64 * m - 2048 * (p - 1)) + (int64_t)(c - 64 * p) * (m - 64 * p) - 64 * p;
+}
+__host__ __device__ __forceinline__ int64_t fld(int64_t m, int c) { return m - (c & ~63); }
+// doubles of an m-row front
+inline int64_t front_doubles(int64_t m) {
+    const int64_t P = (m - 1) >> 6, w = m - 64 * P;
+    return fcol(m, (int)(64 * P)) + 64 * P + w * w;
+}
+
 
 // ---------------------------------------------------------------- assembly
 // One work-group per 64 x 64 lower tile of a front: the tile is built in LDS from the entries of K that land
@@ -166,6 +187,7 @@ __global__ __launch_bounds__(NT) void front_assemble(int tile0, const int32_t* _
                                                      const int64_t* __restrict__ rel_off,
                                                      const int32_t* __restrict__ rel, double* __restrict__ fronts) {
     __shared__ double T[TB * TB];
+    __shared__ int64_t coff[TB];  // per column of the current child rectangle: where its update entries start
     const int item = tile0 + blockIdx.x;
     const int s = tile_sn[item];
     const int tr = tile_rc[item] >> 16, tc = tile_rc[item] & 0xffff;
@@ -180,23 +202,23 @@ __global__ __launch_bounds__(NT) void front_assemble(int tile0, const int32_t* _
         const int c = rec[0], ra = rec[1], rb = rec[2], ca = rec[3], cb = rec[4];
         const int nc = ncol[c], mc = mrows[c];
         const int32_t* rl = rel + rel_off[c];
-        const int nr = rb - ra, ncc = cb - ca;
-        {
-            const double* F = fronts + foff[c];
-            for (int e = threadIdx.x; e < nr * ncc; e += NT) {
-                const int ui = ra + e % nr, uj = ca + e / nr;
-                if (ui >= uj) {
-                    const double u = F[(int64_t)(nc + ui) + (int64_t)mc * (nc + uj)];
-                    T[(rl[ui] - r0) + TB * (rl[uj] - c0)] += u;
-                }
+        const int nr = rb - ra, ncc = cb - ca;  // ncc <= 64: the columns map to distinct columns of the tile
+        if (threadIdx.x < ncc) coff[threadIdx.x] = foff[c] + fcol(mc, nc + ca + threadIdx.x) + nc;
+        __syncthreads();
+        for (int e = threadIdx.x; e < nr * ncc; e += NT) {
+            const int ui = ra + e % nr, uj = ca + e / nr;
+            if (ui >= uj) {
+                const double u = fronts[coff[uj - ca] + ui];
+                T[(rl[ui] - r0) + TB * (rl[uj] - c0)] += u;
             }
         }
         __syncthreads();
     }
-    double* F = fronts + foff[s];
+    double* F = fronts + foff[s] + fcol(m, c0);  // the tile's columns lie in one panel
+    const int64_t ld = fld(m, c0);
     for (int e = threadIdx.x; e < TB * TB; e += NT) {
         const int i = r0 + e % TB, j = c0 + e / TB;
-        if (i < m && j < m && i >= j) F[(int64_t)i + (int64_t)m * j] = T[e];
+        if (i < m && j < m && i >= j) F[i + ld * (j - c0)] = T[e];
     }
 }
 
@@ -244,7 +266,7 @@ __global__ __launch_bounds__(NT) void front_small(const int32_t* __restrict__ li
     __shared__ int bad;
     const int s = list[blockIdx.x];
     const int m = mrows[s], nn = ncol[s];
-    double* F = fronts + foff[s];
+    double* F = fronts + foff[s];  // m <= 64: a plain column-major square
     if (threadIdx.x == 0) bad = -1;
     for (int e = threadIdx.x; e < m * m; e += NT) {
         const int i = e % m, j = e / m;
@@ -361,7 +383,8 @@ __device__ __forceinline__ void potrf_block(int s, int k0, int slot, const int32
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
     const int m = mrows[s];
     const int kb = min(TB, ncol[s] - k0);
-    double* F = fronts + foff[s] + (int64_t)k0 + (int64_t)m * k0;
+    double* F = fronts + foff[s] + fcol(m, k0) + k0;  // the block's panel, column stride ld
+    const int64_t ld = fld(m, k0);
     const int p0 = first[s] + k0;
     int* badmin = flags;
     int* ready = flags + 1;
@@ -373,7 +396,7 @@ __device__ __forceinline__ void potrf_block(int s, int k0, int slot, const int32
 #pragma unroll
     for (int c = 0; c < PW; c++) {
         const int j = PW * w + c;
-        a[c] = (j < kb && lane < kb) ? (j <= lane ? F[lane + (int64_t)m * j] : 0.0) : (j == lane ? 1.0 : 0.0);
+        a[c] = (j < kb && lane < kb) ? (j <= lane ? F[lane + ld * j] : 0.0) : (j == lane ? 1.0 : 0.0);
     }
     __syncthreads();
     // columns of the waves before this one, in order, each as soon as the counter covers it (bounded: the
@@ -409,7 +432,7 @@ __device__ __forceinline__ void potrf_block(int s, int k0, int slot, const int32
 #pragma unroll
     for (int c = 0; c < PW; c++) {
         const int j = PW * w + c;
-        if (j < kb && lane < kb && j <= lane) F[lane + (int64_t)m * j] = a[c];
+        if (j < kb && lane < kb && j <= lane) F[lane + ld * j] = a[c];
         Lc[TB * j] = j <= lane ? a[c] : 0.0;
     }
     // lane i of the wave owning column i holds that pivot's reciprocal
@@ -483,7 +506,8 @@ __global__ __launch_bounds__(NT) void blk_trsm_mma(const int32_t* __restrict__ i
     }
     const int row = k0 + kb + rb * TR + 16 * wave + li;
     const bool rowok = row < m;
-    double* X = fronts + foff[s] + (rowok ? row : 0) + (int64_t)m * k0;  // X[m j] = entry (row, k0 + j)
+    const int64_t ld = fld(m, k0);
+    double* X = fronts + foff[s] + fcol(m, k0) + (rowok ? row : 0);  // X[ld j] = entry (row, k0 + j)
     double4_t y[4];
     __syncthreads();
 #pragma unroll
@@ -492,7 +516,7 @@ __global__ __launch_bounds__(NT) void blk_trsm_mma(const int32_t* __restrict__ i
 #pragma unroll
         for (int r = 0; r < 4; r++) {
             const int j = 16 * b + lk + 4 * r;
-            acc[r] = (rowok && j < kb) ? X[(int64_t)m * j] : 0.0;
+            acc[r] = (rowok && j < kb) ? X[ld * j] : 0.0;
         }
 #pragma unroll
         for (int a = 0; a < b; a++)
@@ -512,7 +536,7 @@ __global__ __launch_bounds__(NT) void blk_trsm_mma(const int32_t* __restrict__ i
 #pragma unroll
             for (int r = 0; r < 4; r++) {
                 const int j = 16 * b + lk + 4 * r;
-                if (j < kb) X[(int64_t)m * j] = y[b][r];
+                if (j < kb) X[ld * j] = y[b][r];
             }
 }
 constexpr int KC = 16;
@@ -545,30 +569,46 @@ __device__ __forceinline__ void tile_mma(double* __restrict__ F, int m, int ri0,
     // D layout of the 16x16x4 f64 MFMA: item r of a lane is row (lane / 16) + 4 r, column lane % 16 of the
     // product block; operands are swapped below so the block is C^T: C row = lane % 16, C column =
     // (lane / 16) + 4 r (16 consecutive rows of a column per 16-lane group)
+    // The wave's 16 CB <= 64 columns rj0 + qc + jl lie in at most two panels: the first `cut` of them in the
+    // panel of column rj0 + qc, the rest at the start of the next one.
+    const int cw = rj0 + qc, cut = ((cw | 63) + 1) - cw;
+    const int64_t f0 = fcol(m, cw), f1 = fcol(m, cw + cut);
+    const int ld0 = (int)fld(m, cw), ld1 = ld0 - 64;
+    // Only a front's last blocked step (pivot count not a multiple of 64) has its columns off the panel grid,
+    // so the tile's loads and stores take a wave-uniform branch to the form with the per-column choice.
     double4_t acc[RB][CB];
+    auto load = [&](auto split) {
 #pragma unroll
-    for (int a = 0; a < RB; a++)
+        for (int a = 0; a < RB; a++)
 #pragma unroll
-        for (int b = 0; b < CB; b++)
+            for (int b = 0; b < CB; b++)
 #pragma unroll
-            for (int r = 0; r < 4; r++) {
-                const int i = qr + 16 * a + li;
-                const int j = qc + 16 * b + lk + 4 * r;
-                const int gi = ri0 + i, gj = rj0 + j;
-                acc[a][b][r] = (active && i < nri && j < nrj && gi >= gj) ? F[(int64_t)gi + (int64_t)m * gj] : 0.0;
-            }
+                for (int r = 0; r < 4; r++) {
+                    const int i = qr + 16 * a + li;
+                    const int jl = 16 * b + lk + 4 * r, j = qc + jl;
+                    const int gi = ri0 + i, gj = rj0 + j;
+                    const int64_t o = (!decltype(split)::value || jl < cut) ? f0 + jl * ld0 : f1 + (jl - cut) * ld1;
+                    acc[a][b][r] = (active && i < nri && j < nrj && gi >= gj) ? F[o + gi] : 0.0;
+                }
+    };
+    if (cut == TB)
+        load(std::false_type{});
+    else
+        load(std::true_type{});
     // the panel slices go through LDS in halves of KH columns (columns past kb are zero; a half that starts
     // at or past kb is skipped).  Each half is fetched into registers while the previous half's MFMAs run,
     // then written to LDS, so the panel loads' latency hides under the arithmetic.
     constexpr int PER = ST * KH / NT;  // panel entries per thread per half (each of Pi and Pj)
     double fa[PER], fb[PER];
     auto fetch = [&](int h0) {
+        // the KH columns of a half lie in one panel (k0 and h0 are multiples of KH)
+        const int64_t cb = fcol(m, k0 + h0), ld = fld(m, k0 + h0);
 #pragma unroll
         for (int q = 0; q < PER; q++) {
             const int e = threadIdx.x + q * NT;
             const int r = e % ST, t = e / ST;
             const bool in = h0 + t < kb;
-            const int64_t col = (int64_t)m * (k0 + h0 + t);
+            const int64_t col = cb + ld * t;
             fa[q] = (in && r < nri) ? F[(int64_t)(ri0 + r) + col] : 0.0;
             fb[q] = (in && r < nrj) ? F[(int64_t)(rj0 + r) + col] : 0.0;
         }
@@ -604,7 +644,7 @@ __device__ __forceinline__ void tile_mma(double* __restrict__ F, int m, int ri0,
             }
         }
     }
-    if (active) {
+    auto store = [&](auto split) {
 #pragma unroll
         for (int a = 0; a < RB; a++)
 #pragma unroll
@@ -612,10 +652,17 @@ __device__ __forceinline__ void tile_mma(double* __restrict__ F, int m, int ri0,
 #pragma unroll
                 for (int r = 0; r < 4; r++) {
                     const int i = qr + 16 * a + li;
-                    const int j = qc + 16 * b + lk + 4 * r;
+                    const int jl = 16 * b + lk + 4 * r, j = qc + jl;
                     const int gi = ri0 + i, gj = rj0 + j;
-                    if (i < nri && j < nrj && gi >= gj) F[(int64_t)gi + (int64_t)m * gj] = acc[a][b][r];
+                    const int64_t o = (!decltype(split)::value || jl < cut) ? f0 + jl * ld0 : f1 + (jl - cut) * ld1;
+                    if (i < nri && j < nrj && gi >= gj) F[o + gi] = acc[a][b][r];
                 }
+    };
+    if (active) {
+        if (cut == TB)
+            store(std::false_type{});
+        else
+            store(std::true_type{});
     }
 }
 
@@ -775,7 +822,7 @@ __global__ __launch_bounds__(NT, 2) void dense_front(int64_t t0, int64_t t1, Den
                 for (int r = 0; r < 4; r++) {
                     const int i = qr + 16 * a + li, j = qc + 16 * b + lk + 4 * r;
                     const bool in = active && i < nri && j < nrj && (!diag || i >= j);
-                    acc[a][b][r] = in ? F[(int64_t)(ri0 + i) + (int64_t)m * (rj0 + j)] : 0.0;
+                    acc[a][b][r] = in ? F[fcol(m, rj0 + j) + (ri0 + i)] : 0.0;
                 }
         // left-looking: every pivot block before this tile's column
         const int kmax = min(bj, np);
@@ -787,8 +834,8 @@ __global__ __launch_bounds__(NT, 2) void dense_front(int64_t t0, int64_t t1, Den
                 const int r = e % DT, c = e / DT;
                 double av = 0.0, bv = 0.0;
                 if (c < kk) {
-                    if (r < nri) av = F[(int64_t)(ri0 + r) + (int64_t)m * (kc0 + c)];
-                    if (!diag && r < nrj) bv = F[(int64_t)(rj0 + r) + (int64_t)m * (kc0 + c)];
+                    if (r < nri) av = F[fcol(m, kc0 + c) + (ri0 + r)];
+                    if (!diag && r < nrj) bv = F[fcol(m, kc0 + c) + (rj0 + r)];
                 }
                 Pa[c * LDT + r] = -av;
                 Pb[c * LDT + r] = bv;
@@ -823,7 +870,7 @@ __global__ __launch_bounds__(NT, 2) void dense_front(int64_t t0, int64_t t1, Den
                         for (int r = 0; r < 4; r++) {
                             const int i = qr + 16 * a + li, j = qc + 16 * b + lk + 4 * r;
                             if (i < nri && j < nrj && (!diag || i >= j))
-                                F[(int64_t)(ri0 + i) + (int64_t)m * (rj0 + j)] = acc[a][b][r];
+                                F[fcol(m, rj0 + j) + (ri0 + i)] = acc[a][b][r];
                         }
             continue;
         }
@@ -838,7 +885,7 @@ __global__ __launch_bounds__(NT, 2) void dense_front(int64_t t0, int64_t t1, Den
 #pragma unroll
                         for (int r = 0; r < 4; r++) {
                             const int i = qr + 16 * a + li, j = qc + 16 * b + lk + 4 * r;
-                            if (i < nri && j < nrj && i >= j) F[(int64_t)(ri0 + i) + (int64_t)m * (rj0 + j)] = acc[a][b][r];
+                            if (i < nri && j < nrj && i >= j) F[fcol(m, rj0 + j) + (ri0 + i)] = acc[a][b][r];
                         }
             __syncthreads();  // the tile's stores are visible to the work-group; LDS is free
             potrf_block(s, rj0, slot, first, ncol, mrows, foff, fronts, D.tdiag, D.trdiag, status,
@@ -905,7 +952,7 @@ __global__ __launch_bounds__(NT, 2) void dense_front(int64_t t0, int64_t t1, Den
 #pragma unroll
                 for (int r = 0; r < 4; r++) {
                     const int j = 16 * b + lk + 4 * r;
-                    if (j < kb) F[(int64_t)(ri0 + row) + (int64_t)m * (rj0 + j)] = yb[b][r];
+                    if (j < kb) F[fcol(m, rj0 + j) + (ri0 + row)] = yb[b][r];
                 }
         publish_final(myflag, epoch);
     }
@@ -979,13 +1026,16 @@ __global__ __launch_bounds__(NT) void solve_fwd(const int32_t* __restrict__ list
     const int lane = threadIdx.x % 64;
     for (int j0 = 0; j0 < nn; j0 += SCB) {
         const int cb = min(SCB, nn - j0);
+        // the block's columns lie in one panel: column j0 + t at Lb + ld t
+        const double* Lb = L + fcol(m, j0);
+        const int64_t ld = fld(m, j0);
         if (threadIdx.x < 64) {
             const bool act = lane < cb;
             double a[SCB];  // lane p: a[t] = L(j0 + p, j0 + t), t < p
 #pragma unroll
-            for (int t = 0; t < SCB; t++) a[t] = (act && t < lane) ? L[(j0 + lane) + (int64_t)m * (j0 + t)] : 0.0;
+            for (int t = 0; t < SCB; t++) a[t] = (act && t < lane) ? Lb[(j0 + lane) + ld * t] : 0.0;
             double wp = act ? w[j0 + lane] : 0.0;
-            const double rp = act ? 1.0 / L[(j0 + lane) + (int64_t)m * (j0 + lane)] : 1.0;
+            const double rp = act ? 1.0 / Lb[(j0 + lane) + ld * lane] : 1.0;
 #pragma unroll
             for (int t = 0; t < SCB; t++) {
                 const double z = lane_value(wp, t) * lane_value(rp, t);
@@ -997,7 +1047,7 @@ __global__ __launch_bounds__(NT) void solve_fwd(const int32_t* __restrict__ list
         for (int i = j0 + cb + threadIdx.x; i < mr; i += NT) {
             double lv[SCB];
 #pragma unroll
-            for (int t = 0; t < SCB; t++) lv[t] = t < cb ? L[i + (int64_t)m * (j0 + t)] : 0.0;
+            for (int t = 0; t < SCB; t++) lv[t] = t < cb ? Lb[i + ld * t] : 0.0;
             double acc = w[i];
 #pragma unroll
             for (int t = 0; t < SCB; t++)
@@ -1037,9 +1087,11 @@ __global__ __launch_bounds__(NT) void solve_fwd_rows(const int32_t* __restrict__
     double acc = row_gather(0.0, gp[i], gp[i + 1], gsrc, upd);
     const double* L = fronts + foff[s] + i;
     for (int j0 = 0; j0 < nn; j0 += SCB) {
+        const double* Lb = L + fcol(m, j0);  // the block's columns lie in one panel
+        const int64_t ld = fld(m, j0);
         double lv[SCB];
 #pragma unroll
-        for (int t = 0; t < SCB; t++) lv[t] = j0 + t < nn ? L[(int64_t)m * (j0 + t)] : 0.0;
+        for (int t = 0; t < SCB; t++) lv[t] = j0 + t < nn ? Lb[ld * t] : 0.0;
 #pragma unroll
         for (int t = 0; t < SCB; t++)
             if (j0 + t < nn) acc = fma(-lv[t], zs[j0 + t], acc);
@@ -1088,7 +1140,7 @@ __global__ __launch_bounds__(NT) void solve_bwd(const int32_t* __restrict__ list
         __syncthreads();
         for (int j = wv; j < nn; j += NT / 64) {
             // four independent partial sums per lane, so that four loads of the column are in flight
-            const double* col = L + (int64_t)m * j + r0;
+            const double* col = L + fcol(m, j) + r0;
             double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
             int t = ln;
             for (; t + 192 < nr; t += 256) {
@@ -1113,10 +1165,11 @@ __global__ __launch_bounds__(NT) void solve_bwd(const int32_t* __restrict__ list
         if (threadIdx.x < 64) {
             const bool act = ln < cb;
             double a[SCB];  // lane q: a[t] = L(j0 + t, j0 + q), t > q
+            const double* Lq = L + fcol(m, j0 + (act ? ln : 0));  // column j0 + ln
 #pragma unroll
-            for (int t = 0; t < SCB; t++) a[t] = (act && t > ln && t < cb) ? L[(j0 + t) + (int64_t)m * (j0 + ln)] : 0.0;
+            for (int t = 0; t < SCB; t++) a[t] = (act && t > ln && t < cb) ? Lq[j0 + t] : 0.0;
             double wq = act ? w[j0 + ln] : 0.0;
-            const double rq = act ? 1.0 / L[(j0 + ln) + (int64_t)m * (j0 + ln)] : 1.0;
+            const double rq = act ? 1.0 / Lq[j0 + ln] : 1.0;
 #pragma unroll
             for (int t = SCB - 1; t >= 0; t--) {
                 if (t >= cb) continue;
@@ -1128,8 +1181,9 @@ __global__ __launch_bounds__(NT) void solve_bwd(const int32_t* __restrict__ list
         __syncthreads();
         for (int i = threadIdx.x; i < j0; i += NT) {
             double lv[SCB];
+            const double* Li = L + fcol(m, i) + j0;  // column i from row j0
 #pragma unroll
-            for (int t = 0; t < SCB; t++) lv[t] = t < cb ? L[(j0 + t) + (int64_t)m * i] : 0.0;
+            for (int t = 0; t < SCB; t++) lv[t] = t < cb ? Li[t] : 0.0;
             double acc = w[i];
 #pragma unroll
             for (int t = SCB - 1; t >= 0; t--)
@@ -1186,7 +1240,7 @@ __global__ __launch_bounds__(NT) void solve_bwd_dots(const int32_t* __restrict__
         double a[KW][4];
 #pragma unroll
         for (int k = 0; k < KW; k++) {
-            col[k] = L + (int64_t)m * (on[k] ? SCB * cb + wv + 4 * k : 0) + r0;
+            col[k] = L + fcol(m, on[k] ? SCB * cb + wv + 4 * k : 0) + r0;
             a[k][0] = a[k][1] = a[k][2] = a[k][3] = 0.0;
         }
         int t = ln;
@@ -1310,10 +1364,11 @@ __global__ __launch_bounds__(64) void wide_inverse(const int32_t* __restrict__ i
     const int64_t ob = items[3 * blockIdx.x + 2];
     const int m = mrows[s], nn = ncol[s];
     const int r0 = SB * g, nb = min(SB, nn - r0);
-    const double* L = fronts + foff[s] + r0 + (int64_t)m * r0;
+    const double* L = fronts + foff[s] + fcol(m, r0) + r0;  // the block's panel, column stride ld
+    const int64_t ld = fld(m, r0);
     const int j = threadIdx.x;
     for (int k = 0; k < SB; k++)
-        Ls[j * SB + k] = (j < nb && k < nb) ? (j >= k ? L[j + (int64_t)m * k] : 0.0) : (j == k ? 1.0 : 0.0);
+        Ls[j * SB + k] = (j < nb && k < nb) ? (j >= k ? L[j + ld * k] : 0.0) : (j == k ? 1.0 : 0.0);
     __syncthreads();
     ri[j] = 1.0 / Ls[j * SB + j];
     __syncthreads();
@@ -1360,7 +1415,7 @@ __global__ __launch_bounds__(NT) void wide_fwd(int s, double* __restrict__ zx, i
     const double* L = fronts + foff[s];
     const int i = threadIdx.x % 64, q = threadIdx.x / 64;
     const bool rowok = i < nr;
-    const double* Lr = L + (rowok ? r0 + i : 0);  // row r0 + i, column stride m
+    const double* Lr = L + (rowok ? r0 + i : 0);  // row r0 + i
     // row i of the inverse of the own diagonal block (wave 0, read before any wait; zero above the diagonal)
     double v[SB];
     const double* Vi = winv + (int64_t)g * SB * SB + i;  // Vi[64 j] = inv(L_gg)(i, j)
@@ -1371,11 +1426,13 @@ __global__ __launch_bounds__(NT) void wide_fwd(int s, double* __restrict__ zx, i
     bool alive = true;
     for (int c = 0; c < ncb; c++) {
         const int c0 = SB * c, kc = min(SB, nn - c0);
+        const double* Lc = Lr + fcol(m, c0);  // block c is one panel: column c0 + j at Lc + ld j
+        const int64_t ld = fld(m, c0);
         double lv[16];
 #pragma unroll
         for (int jj = 0; jj < 16; jj++) {
             const int j = 16 * q + jj;
-            lv[jj] = (rowok && j < kc) ? Lr[(int64_t)m * (c0 + j)] : 0.0;
+            lv[jj] = (rowok && j < kc) ? Lc[ld * j] : 0.0;
         }
         const double zv = take_block_wave(zx, c, fault, alive);
 #pragma unroll
@@ -1425,7 +1482,7 @@ __global__ __launch_bounds__(NT) void wide_bwd(int s, double* __restrict__ zx, i
     const int32_t* R = rows + roff[s];
     const int j = threadIdx.x % 64, q = threadIdx.x / 64;
     const bool colok = j < kb;
-    const double* Lc = fronts + foff[s] + (int64_t)m * (c0 + (colok ? j : 0));  // column c0 + j
+    const double* Lc = fronts + foff[s] + fcol(m, c0 + (colok ? j : 0));  // column c0 + j
     // column j of the inverse of the own diagonal block (wave 0; zero above the diagonal of the inverse)
     double v[SB];
     const double* Vj = winv + (int64_t)b * SB * SB + (int64_t)SB * j;  // Vj[t] = inv(L_bb)(t, j)
@@ -1506,7 +1563,7 @@ static void build_numeric_plan(chol_sym* C, const std::vector<int32_t>& colptr, 
         C->h_foff[s] = fo;
         C->h_roff[s] = S.rows_ptr[s];
         C->h_uoff[s] = uo;
-        fo += m * m;
+        fo += front_doubles(m);
         uo += m - nn;
         nnzl += (int64_t)nn * m - (int64_t)nn * (nn - 1) / 2;
         for (int j = 0; j < nn; j++) {
@@ -2555,7 +2612,7 @@ extern "C" int chol_export_factor(chol_sym* C, int64_t* lp, int32_t* li, double*
             for (int jc = 0; jc < nn; jc++) {
                 for (int jr = jc; jr < m; jr++) {
                     li[q] = R[jr];
-                    if (lx) lx[q] = F[C->h_foff[s] + jr + (int64_t)m * jc];
+                    if (lx) lx[q] = F[C->h_foff[s] + fcol(m, jc) + jr];
                     q++;
                 }
                 lp[f + jc + 1] = q;

@@ -74,15 +74,21 @@ constexpr int SEG_CPW = 4;  // chunks per wave range (a range is extended to the
 // c (sigma_x[c] + dw).
 constexpr uint64_t KT_HESS = 0xFFFFF, KT_DIAG = 0xFFFFE, KT_ZERO = 0xFFFFD;  // KT_ZERO: padding, value 0
 
+// Evaluated without branches: every lane issues its three loads at once (lanes of other kinds read entry 0,
+// which every model has, and discard it), so a chunk costs one memory round trip whatever its mix of kinds.
 struct KEval {
     const double *jac, *dvec, *hess, *sigx;
     double dw;
     __device__ __forceinline__ double operator()(uint64_t u) const {
         const uint64_t r = u >> 44;
-        if (r == KT_HESS) return hess[u & 0xFFFFFFFFFFFull];
-        if (r == KT_DIAG) return sigx[u & 0x3FFFFF] + dw;
-        if (r == KT_ZERO) return 0.0;
-        return jac[u & 0x3FFFFF] * dvec[r] * jac[(u >> 22) & 0x3FFFFF];
+        const bool hs = r == KT_HESS, dg = r == KT_DIAG, pr = r < KT_ZERO;
+        const double* p1 = hs ? hess + (u & 0xFFFFFFFFFFFull) : dg ? sigx + (u & 0x3FFFFF) : jac + (pr ? u & 0x3FFFFF : 0);
+        const double x1 = *p1;
+        const double x2 = dvec[pr ? r : 0];
+        const double x3 = jac[pr ? (u >> 22) & 0x3FFFFF : 0];
+        asm volatile("" ::"v"(x1), "v"(x2), "v"(x3));  // keeps the compiler from sinking the loads into branches
+        const double prod = (x1 * x2) * x3;  // J_a D_r J_b, in that order
+        return pr ? prod : dg ? x1 + dw : hs ? x1 : 0.0;
     }
 };
 
@@ -91,7 +97,10 @@ constexpr uint64_t PROD_ZERO = ~0ull;
 struct ProdEval {
     const double *a, *b;
     __device__ __forceinline__ double operator()(uint64_t u) const {
-        return u == PROD_ZERO ? 0.0 : a[(uint32_t)u] * b[(uint32_t)(u >> 32)];
+        const bool z = u == PROD_ZERO;
+        const double xa = a[z ? 0u : (uint32_t)u], xb = b[z ? 0u : (uint32_t)(u >> 32)];
+        asm volatile("" ::"v"(xa), "v"(xb));  // both loads in flight together, whatever the lane's kind
+        return z ? 0.0 : xa * xb;
     }
 };
 
@@ -108,9 +117,25 @@ __global__ __launch_bounds__(KB) void seg_gather(int nwaves, const int32_t* __re
     const int lane = threadIdx.x % 64;
     const uint64_t below = lane == 63 ? ~0ull : ((2ull << lane) - 1);  // lanes 0..lane
     double carry = 0.0;
-    for (int c = wptr[w]; c < wptr[w + 1]; c++) {
-        double v = ev(term[(int64_t)c * 64 + lane]);
-        const uint64_t sm = smask[c], em = emask[c];
+    // the chunk range and each chunk's masks and first output are wave-uniform (scalar loads); the next chunk's
+    // term codes are fetched while the current chunk's values are gathered, and the output index of a lane
+    // that ends a segment is looked up together with those values
+    const int c0 = __builtin_amdgcn_readfirstlane(wptr[w]), c1 = __builtin_amdgcn_readfirstlane(wptr[w + 1]);
+    uint64_t tn = term[(int64_t)c0 * 64 + lane], smn = smask[c0], emn = emask[c0];
+    int bn = base[c0];
+    for (int c = c0; c < c1; c++) {
+        const uint64_t t = tn, sm = smn, em = emn;
+        const int bs = bn;
+        if (c + 1 < c1) {
+            tn = term[(int64_t)(c + 1) * 64 + lane];
+            smn = smask[c + 1];
+            emn = emask[c + 1];
+            bn = base[c + 1];
+        }
+        const bool ends = (em >> lane) & 1;
+        const int so = bs + __popcll(sm & below & ~1ull);  // segment (output) ordinal
+        const int o = segout && ends ? segout[so] : so;
+        double v = ev(t);
         int f = (int)((sm >> lane) & 1);
         if (lane == 0 && !f) v += carry;  // the output continued from the previous chunk
 #pragma unroll
@@ -122,11 +147,7 @@ __global__ __launch_bounds__(KB) void seg_gather(int nwaves, const int32_t* __re
                 f |= fp;
             }
         }
-        if ((em >> lane) & 1) {
-            const int so = base[c] + __popcll(sm & below & ~1ull);  // segment (output) ordinal
-            const int o = segout ? segout[so] : so;
-            out[o] = add ? add[o] + v : v;
-        }
+        if (ends) out[o] = add ? add[o] + v : v;
         carry = __shfl(v, 63);
     }
 }

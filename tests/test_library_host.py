@@ -125,3 +125,21 @@ def test_serving_defaults_and_argument_checks():
     assert O.lib().opf_serve_submit(None, None, 0) == O.E_INVALID
     assert O.lib().opf_serve_destroy(None) == O.OK
     assert O.lib().opf_serve_now() > 0
+
+
+def test_factor_storage_is_the_lower_block_trapezoid():
+    """Each front keeps only its lower part: 64-column panels, panel p holding rows 64p.. of its columns, so
+    the device factor takes about half the bytes of full m x m squares."""
+    g = gridgen.make_config("cfg1")
+    M = opf().Model(g)
+    cp, ri = M.kkt_pattern()
+    C = opf().Cholesky(M.n, cp, ri, opf().chol_options(**OPTS))
+    rp, _ = C.supernode_rows()
+    total = square = 0
+    for m in np.diff(rp).tolist():
+        square += m * m
+        for c0 in range(0, m, 64):
+            total += min(64, m - c0) * (m - c0)
+    assert C.factor_bytes == 8 * total
+    assert max(np.diff(rp)) > 1000  # a front large enough for the halving to show
+    assert C.factor_bytes < 0.7 * 8 * square  # small fronts (m <= 64) stay whole squares
