@@ -178,6 +178,15 @@ typedef struct {
      * step applies all of them to the rest of the front as one update of
      * rank 64 * pair_panels */
     int32_t pair_panels;
+    /* 0 (default): Cholesky, P K P^T = L L^T.  1: the LU factorization with
+     * this fixed pivot sequence (the refactorization alternative of Section
+     * VI), held in its symmetric form P K P^T = L D L^T (U = D L^T): L unit
+     * lower, D diagonal.  A pivot is then rejected when |d| <= pivot_tol *
+     * |K_jj| (pivot_tol 0: when it is zero or not finite); negative pivots
+     * are accepted, so an indefinite K whose leading principal minors are
+     * nonzero factors, and chol_inertia reports the signs of D.  Not with
+     * tile_min > 0. */
+    int32_t ldlt;
 } chol_options;
 
 typedef struct chol_sym chol_sym;
@@ -199,13 +208,20 @@ int chol_perm(const chol_sym* sym, int32_t* perm);
 int chol_etree(const chol_sym* sym, int32_t* parent, int32_t* colcount);
 int chol_supernodes(const chol_sym* sym, int32_t* snode_ptr);
 int chol_supernode_rows(const chol_sym* sym, int64_t* rows_ptr, int32_t* rows);
-/* Numeric factorization of P K P^T = L L^T from device values kval [nnz]
- * in the analyzed pattern's order.  Synchronises the stream; returns
+/* Numeric factorization of P K P^T = L L^T (or L D L^T, see ldlt) from
+ * device values kval [nnz] in the analyzed pattern's order.  Synchronises
+ * the stream; returns
  * OPF_E_NOT_PD and *bad_col = pivot index of the first rejected pivot
  * (see pivot_tol; the smallest such index within the first failing
  * elimination level), else OPF_OK and *bad_col = -1.  The factor stays in
  * HBM. */
 int chol_factor(chol_sym* sym, const double* kval, void* stream, int32_t* bad_col);
+/* Inertia of K from the last successful factorization (host outputs): npos
+ * positive and nneg negative pivots, npos + nneg = n.  By Sylvester's law of
+ * inertia these are K's numbers of positive and negative eigenvalues.  A
+ * Cholesky factorization succeeds only for npos = n.  OPF_E_STATE without a
+ * successful factorization. */
+int chol_inertia(const chol_sym* sym, int64_t* npos, int64_t* nneg);
 /* Diagnostics (process-wide, since load): how many factorization and solve
  * launch sequences were captured into HIP graphs (handles an IPM owns, on a
  * stream of its own), and how many of those captures failed and were
@@ -251,7 +267,9 @@ int chol_solve_noalloc(chol_sym* sym, const double* b, double* x, int32_t nrhs, 
 int chol_timing(chol_sym* sym, int mask);
 int chol_timing_read(const chol_sym* sym, double* ms, int64_t* launches, double* flops, double* bytes);
 /* Copy L to the host as CSC in pivot order over the supernodal pattern
- * (lp [n+1], li [nnz_l], lx [nnz_l]); explicit zeros included. */
+ * (lp [n+1], li [nnz_l], lx [nnz_l]); explicit zeros included.  For an
+ * L D L^T factorization (ldlt) the diagonal entries are the pivots of D and
+ * the entries below are L's (whose diagonal is 1). */
 int chol_export_factor(chol_sym* sym, int64_t* lp, int32_t* li, double* lx);
 
 /* ------------------------------------------------------------------------

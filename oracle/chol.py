@@ -38,6 +38,9 @@ def lib():
         L.oracle_chol_factor.argtypes = [ctypes.c_void_p, F64P, ctypes.c_double]
         L.oracle_chol_factor.restype = ctypes.c_int
         L.oracle_chol_solve.argtypes = [ctypes.c_void_p, F64P, F64P]
+        L.oracle_ldlt_factor.argtypes = [ctypes.c_void_p, F64P, ctypes.c_double]
+        L.oracle_ldlt_factor.restype = ctypes.c_int
+        L.oracle_ldlt_solve.argtypes = [ctypes.c_void_p, F64P, F64P]
         _lib = L
     return _lib
 
@@ -134,21 +137,32 @@ class Cholesky:
     def nnz(self):
         return int(lib().oracle_chol_nnz(self._h))
 
-    def factor(self, values, piv_tol=0.0):
-        """Returns -1 if every pivot exceeds piv_tol * |K_jj| (0: positive definite), else the first
-        failing pivot column (permuted numbering)."""
+    def factor(self, values, piv_tol=0.0, ldlt=False):
+        """Returns -1 if every pivot is accepted, else the first failing pivot column (permuted numbering).
+        Cholesky: a pivot is accepted when it exceeds piv_tol * |K_jj| (0: K positive definite).  ``ldlt``: the
+        LU factorization with the fixed pivot sequence in its symmetric form L D L^T, a pivot accepted when
+        |d| exceeds piv_tol * |K_jj| (0: when it is nonzero); the factor then holds D on its diagonal."""
         v, vp = _f64(values)
         assert v.shape[0] == self._ri.shape[0]
-        rc = lib().oracle_chol_factor(self._h, vp, float(piv_tol))
+        fn = lib().oracle_ldlt_factor if ldlt else lib().oracle_chol_factor
+        rc = fn(self._h, vp, float(piv_tol))
         if rc < 0:
-            raise MemoryError("oracle_chol_factor failed")
+            raise MemoryError("oracle factorization failed")
+        self._ldlt = bool(ldlt)
         return -1 if rc == 0 else rc - 1
 
     def solve(self, b):
         b, bp = _f64(b)
         x = np.zeros(self.n)
-        lib().oracle_chol_solve(self._h, bp, x.ctypes.data_as(F64P))
+        fn = lib().oracle_ldlt_solve if getattr(self, "_ldlt", False) else lib().oracle_chol_solve
+        fn(self._h, bp, x.ctypes.data_as(F64P))
         return x
+
+    def inertia(self):
+        """(positive, negative) pivot counts of the last L D L^T factorization."""
+        lp, _, lx = self.export()
+        d = lx[lp[:-1]]
+        return int((d > 0).sum()), int((d < 0).sum())
 
     def export(self):
         """(colptr, rowind, values) of L in the permuted numbering."""

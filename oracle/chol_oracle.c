@@ -34,6 +34,15 @@
  *              L(j,j) = sqrt(A(j,j) - sum_k L(j,k)^2),
  *              L(i,j) = (A(i,j) - sum_k L(i,k) L(j,k)) / L(j,j).
  *   solve      L y = b by columns, then L^T x = y by columns.
+ *   LU         the LU factorization of P K P^T with the same fixed pivot
+ *              sequence (Section VI names LU refactorization beside
+ *              Cholesky), Doolittle's definition: U(k,j) = A(k,j) -
+ *              sum_{t<k} L(k,t) U(t,j), L(i,k) = (A(i,k) - sum_{t<k} L(i,t)
+ *              U(t,k)) / U(k,k).  For symmetric A, U = D L^T with D = diag(U)
+ *              (so U(t,j) = D(t) L(j,t)); the factor keeps L below the
+ *              diagonal and D on it.  A pivot is accepted when |D(j)| >
+ *              piv_tol * |A(j,j)| (piv_tol = 0: when it is nonzero).  Solve:
+ *              L z = b, y = z / D, L^T x = y.
  *
  * Matrices are lower-triangular CSC (column pointers, row indices ascending).
  */
@@ -673,6 +682,72 @@ int oracle_chol_factor(oracle_chol* f, const double* val, double piv_tol) {
     free(w);
     free(bv);
     return status;
+}
+
+/*
+ * LU factorization with the fixed pivot sequence in its symmetric form P K P^T = L D L^T (see the header),
+ * left-looking by columns: w = A(:, j) - sum_{k<j, L(j,k) != 0} L(:, k) U(k, j) with U(k, j) = D(k) L(j, k);
+ * D(j) = w(j), L(i, j) = w(i) / D(j).  lx holds D(j) at the diagonal position.  Returns 0 if every pivot is
+ * accepted, else (1 + j) for the first pivot column j that is not.
+ */
+int oracle_ldlt_factor(oracle_chol* f, const double* val, double piv_tol) {
+    i32 n = f->n;
+    i32 nnz = f->bptr[n];
+    double* w = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    double* bv = (double*)calloc((size_t)(nnz > 0 ? nnz : 1), sizeof(double));
+    if (!w || !bv) {
+        free(w);
+        free(bv);
+        return -1;
+    }
+    for (i32 p = 0; p < nnz; p++) bv[f->amap[p]] = val[p];
+    int status = 0;
+    for (i32 j = 0; j < n; j++) {
+        for (i32 p = f->bptr[j]; p < f->bptr[j + 1]; p++) w[f->bind[p]] = bv[p];
+        for (i32 q = f->rp[j]; q < f->rp[j + 1]; q++) {
+            i32 k = f->rk[q];
+            i32 pj = f->rpos[q]; /* position of L(j,k) */
+            double ukj = f->lx[f->lp[k]] * f->lx[pj]; /* U(k,j) = D(k) L(j,k) */
+            for (i32 p = pj; p < f->lp[k + 1]; p++) w[f->li[p]] -= f->lx[p] * ukj;
+        }
+        double d = w[j];
+        double ajj = bv[f->bptr[j]];
+        if (!(fabs(d) > piv_tol * fabs(ajj))) {
+            status = 1 + j;
+            for (i32 p = f->lp[j]; p < f->lp[j + 1]; p++) w[f->li[p]] = 0.0;
+            break;
+        }
+        f->lx[f->lp[j]] = d;
+        w[j] = 0.0;
+        for (i32 p = f->lp[j] + 1; p < f->lp[j + 1]; p++) {
+            i32 i = f->li[p];
+            f->lx[p] = w[i] / d;
+            w[i] = 0.0;
+        }
+    }
+    free(w);
+    free(bv);
+    return status;
+}
+
+/* x = K^{-1} b from the L D L^T factor (b and x in original numbering; may alias). */
+void oracle_ldlt_solve(const oracle_chol* f, const double* b, double* x) {
+    i32 n = f->n;
+    double* y = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    if (!y) return;
+    for (i32 k = 0; k < n; k++) y[k] = b[f->perm[k]];
+    for (i32 j = 0; j < n; j++) {
+        double yj = y[j];
+        for (i32 p = f->lp[j] + 1; p < f->lp[j + 1]; p++) y[f->li[p]] -= f->lx[p] * yj;
+    }
+    for (i32 j = 0; j < n; j++) y[j] /= f->lx[f->lp[j]];
+    for (i32 j = n - 1; j >= 0; j--) {
+        double s = y[j];
+        for (i32 p = f->lp[j] + 1; p < f->lp[j + 1]; p++) s -= f->lx[p] * y[f->li[p]];
+        y[j] = s;
+    }
+    for (i32 k = 0; k < n; k++) x[f->perm[k]] = y[k];
+    free(y);
 }
 
 /* x = K^{-1} b using the last factor (b and x in original numbering; may alias). */

@@ -94,7 +94,10 @@ struct chol_sym {
 
     DBuf<int32_t> status;
     DBuf<int32_t> level_d;    // elimination level of each supernode
-    DBuf<int64_t> statwords;  // [0]: first rejected pivot as (level << 32 | pivot), INT64_MAX if none
+    DBuf<int64_t> statwords;  // [0]: first rejected pivot as (level << 32 | pivot), INT64_MAX if none;
+                              // [1]: negative pivots of an L D L^T factorization
+    DBuf<double> dval;        // L D L^T: the pivots, in pivot order
+    int64_t last_nneg = 0;    // negative pivots of the last L D L^T factorization
     // host words the factorization status and the fault words are read into: pinned memory lent by the
     // owning IPM (chol_bind_host), else allocated at the first factorization
     int64_t* hwords = nullptr;
@@ -233,35 +236,56 @@ struct PivotRef {
     }
 };
 
+// LDL = false: Cholesky, pivot k accepted when d > threshold, column scaled by sqrt(d).  LDL = true: the
+// symmetric form L D L^T of the LU factorization with this fixed pivot sequence (U = D L^T): pivot k accepted
+// when |d| > threshold (negative pivots are fine), kept on the diagonal and in dval[pivot], the column below
+// divided by d, and the trailing block updated with l_i (d l_j) = l_i w_j, w the column before the division.
+template <bool LDL>
 __device__ __forceinline__ void lds_cholesky(double* A, int lda, int m, int ncols, int* bad_local, PivotRef pr,
-                                             int pivot0) {
+                                             int pivot0, double* __restrict__ dval) {
     // A: lower triangle, column-major in LDS.  Factors ncols pivot columns and
     // applies their Schur update to the trailing (m - ncols) block.
     __shared__ double thr[TB];
+    __shared__ double lcol[LDL ? TB : 1];
     const int ti = threadIdx.x % 64, tj = threadIdx.x / 64;
     if (threadIdx.x < ncols) thr[threadIdx.x] = pr.thresh(pivot0 + threadIdx.x);
     for (int k = 0; k < ncols; k++) {
         __syncthreads();
         double d = A[k + lda * k];
-        if (!(d > thr[k])) {
+        if (!(LDL ? fabs(d) > thr[k] : d > thr[k])) {
             if (threadIdx.x == 0 && *bad_local < 0) *bad_local = k;
             d = 1.0;
         }
-        const double r = sqrt(d);
-        __syncthreads();
-        if (threadIdx.x == 0) A[k + lda * k] = r;
-        for (int i = k + 1 + threadIdx.x; i < m; i += NT) A[i + lda * k] /= r;
-        __syncthreads();
-        for (int j = k + 1 + tj; j < m; j += NT / 64)
-            for (int i = j + ti; i < m; i += 64) A[i + lda * j] -= A[i + lda * k] * A[j + lda * k];
+        if constexpr (LDL) {
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                A[k + lda * k] = d;
+                dval[pivot0 + k] = d;
+            }
+            for (int i = k + 1 + threadIdx.x; i < m; i += NT) lcol[i] = A[i + lda * k] / d;
+            __syncthreads();
+            for (int j = k + 1 + tj; j < m; j += NT / 64)
+                for (int i = j + ti; i < m; i += 64) A[i + lda * j] -= lcol[i] * A[j + lda * k];
+            __syncthreads();
+            for (int i = k + 1 + threadIdx.x; i < m; i += NT) A[i + lda * k] = lcol[i];
+        } else {
+            const double r = sqrt(d);
+            __syncthreads();
+            if (threadIdx.x == 0) A[k + lda * k] = r;
+            for (int i = k + 1 + threadIdx.x; i < m; i += NT) A[i + lda * k] /= r;
+            __syncthreads();
+            for (int j = k + 1 + tj; j < m; j += NT / 64)
+                for (int i = j + ti; i < m; i += 64) A[i + lda * j] -= A[i + lda * k] * A[j + lda * k];
+        }
     }
     __syncthreads();
 }
 
+template <bool LDL>
 __global__ __launch_bounds__(NT) void front_small(const int32_t* __restrict__ list, const int32_t* __restrict__ first,
                                                   const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
                                                   const int64_t* __restrict__ foff, double* __restrict__ fronts,
-                                                  int32_t* __restrict__ status, PivotRef pr) {
+                                                  int32_t* __restrict__ status, PivotRef pr, double* __restrict__ dval) {
     __shared__ double A[TB * TB];
     __shared__ int bad;
     const int s = list[blockIdx.x];
@@ -272,7 +296,7 @@ __global__ __launch_bounds__(NT) void front_small(const int32_t* __restrict__ li
         const int i = e % m, j = e / m;
         if (i >= j) A[i + TB * j] = F[e];
     }
-    lds_cholesky(A, TB, m, nn, &bad, pr, first[s]);
+    lds_cholesky<LDL>(A, TB, m, nn, &bad, pr, first[s], dval);
     for (int e = threadIdx.x; e < m * m; e += NT) {
         const int i = e % m, j = e / m;
         if (i >= j) F[e] = A[i + TB * j];
@@ -318,6 +342,13 @@ __device__ __forceinline__ double rsqrt_refined(double d) {
     return y;
 }
 
+__device__ __forceinline__ double rcp_refined(double d) {
+    double y = __builtin_amdgcn_rcp(d);  // hardware estimate, then two Newton steps for 1/d
+    y = fma(y, fma(-d, y, 1.0), y);
+    y = fma(y, fma(-d, y, 1.0), y);
+    return y;
+}
+
 constexpr unsigned long long SENTINEL_BITS = 0x7ff4dead00000000ULL;
 
 __device__ __forceinline__ bool is_sentinel(double v) {
@@ -326,26 +357,42 @@ __device__ __forceinline__ bool is_sentinel(double v) {
 
 // The 16 pivots of wave W (its columns in a[], every earlier column already applied).  thr: lane k holds
 // pivot k's acceptance threshold.  Returns the first rejected pivot of the block (INT_MAX: none).
-template <int W>
-__device__ __forceinline__ int potrf_own(double (&a)[PW], double thr, double* colbuf, int* ready,
-                                         double& myrinv) {
+// LDL: the L D L^T form (see lds_cholesky): colbuf receives the column before the division by the pivot
+// (w), cinv[k] the pivot's reciprocal, a[] the scaled column with the pivot itself on the diagonal, and the
+// updates subtract l_ik w_jk; the lane of pivot k keeps the pivot in myd.
+template <int W, bool LDL>
+__device__ __forceinline__ int potrf_own(double (&a)[PW], double thr, double* colbuf, double* cinv, int* ready,
+                                         double& myrinv, double& myd) {
     const int lane = threadIdx.x % 64;
     int bad = INT_MAX;
     double d = lane_value(a[0], PW * W);
 #pragma unroll
     for (int c = 0; c < PW; c++) {
         const int k = PW * W + c;
-        if (!(d > lane_value(thr, k))) {
+        if (!(LDL ? fabs(d) > lane_value(thr, k) : d > lane_value(thr, k))) {
             bad = min(bad, k);
             d = 1.0;
         }
-        const double rinv = rsqrt_refined(d);
-        const double lik = lane == k ? d * rinv : a[c] * rinv;
-        if (lane == k) myrinv = rinv;
+        double lik, wik;  // the stored column entry, and the one the updates multiply
+        if constexpr (LDL) {
+            const double rinv = rcp_refined(d);
+            wik = lane == k ? d : a[c];
+            lik = lane == k ? d : a[c] * rinv;
+            if (lane == k) {
+                myrinv = rinv;
+                myd = d;
+                cinv[k] = rinv;
+            }
+        } else {
+            const double rinv = rsqrt_refined(d);
+            lik = lane == k ? d * rinv : a[c] * rinv;
+            wik = lik;
+            if (lane == k) myrinv = rinv;
+        }
         a[c] = lik;
-        colbuf[TB * k + lane] = lik;
+        colbuf[TB * k + lane] = wik;
         if (c + 1 < PW) {
-            a[c + 1] = fma(-lik, lane_value(lik, k + 1), a[c + 1]);
+            a[c + 1] = fma(-lik, lane_value(wik, k + 1), a[c + 1]);
             d = lane_value(a[c + 1], k + 1);
         }
         // entries (16 W + c2, k) for c2 > c + 1, read back as broadcasts in aligned pairs (LDS keeps a wave's
@@ -373,12 +420,15 @@ __device__ __forceinline__ double block_threshold(int s, int k0, const int32_t* 
     return lane < min(TB, ncol[s] - k0) ? pr.thresh(first[s] + k0 + lane) : 0.0;
 }
 
+// LDL: the L D L^T form: the front gets L below the diagonal and the pivots on it, the compact copy L with a
+// unit diagonal, rdiag the pivots' reciprocals and dval the pivots; `cinv` is 64 doubles of LDS.
+template <bool LDL>
 __device__ __forceinline__ void potrf_block(int s, int k0, int slot, const int32_t* __restrict__ first,
                                             const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
                                             const int64_t* __restrict__ foff, double* __restrict__ fronts,
                                             double* __restrict__ ldiag, double* __restrict__ rdiag,
                                             int32_t* __restrict__ status, double thr, double* colbuf,
-                                            int* flags) {
+                                            int* flags, double* cinv, double* __restrict__ dval) {
     const int lane = threadIdx.x % 64;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
     const int m = mrows[s];
@@ -410,7 +460,7 @@ __device__ __forceinline__ void potrf_block(int s, int k0, int slot, const int32
             } while (avail <= k && ++spins < (1 << 22));
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         }
-        const double l0 = colbuf[TB * k + lane];
+        const double l0 = LDL ? colbuf[TB * k + lane] * cinv[k] : colbuf[TB * k + lane];
 #pragma unroll
         for (int q = 0; q < PW / 2; q++) {
             const double2 u = *reinterpret_cast<const double2*>(&colbuf[TB * k + PW * w + 2 * q]);
@@ -418,13 +468,13 @@ __device__ __forceinline__ void potrf_block(int s, int k0, int slot, const int32
             a[2 * q + 1] = fma(-l0, u.y, a[2 * q + 1]);
         }
     }
-    double myrinv = 1.0;
+    double myrinv = 1.0, myd = 1.0;
     int bad;
     switch (w) {
-        case 0: bad = potrf_own<0>(a, thr, colbuf, ready, myrinv); break;
-        case 1: bad = potrf_own<1>(a, thr, colbuf, ready, myrinv); break;
-        case 2: bad = potrf_own<2>(a, thr, colbuf, ready, myrinv); break;
-        default: bad = potrf_own<3>(a, thr, colbuf, ready, myrinv); break;
+        case 0: bad = potrf_own<0, LDL>(a, thr, colbuf, cinv, ready, myrinv, myd); break;
+        case 1: bad = potrf_own<1, LDL>(a, thr, colbuf, cinv, ready, myrinv, myd); break;
+        case 2: bad = potrf_own<2, LDL>(a, thr, colbuf, cinv, ready, myrinv, myd); break;
+        default: bad = potrf_own<3, LDL>(a, thr, colbuf, cinv, ready, myrinv, myd); break;
     }
     if (lane == 0 && bad < kb) atomicMin(badmin, bad);
     // results: the front (valid lower part), the compact copy and the reciprocal pivots
@@ -433,26 +483,34 @@ __device__ __forceinline__ void potrf_block(int s, int k0, int slot, const int32
     for (int c = 0; c < PW; c++) {
         const int j = PW * w + c;
         if (j < kb && lane < kb && j <= lane) F[lane + ld * j] = a[c];
-        Lc[TB * j] = j <= lane ? a[c] : 0.0;
+        if constexpr (LDL)
+            Lc[TB * j] = j < lane ? a[c] : j == lane ? 1.0 : 0.0;
+        else
+            Lc[TB * j] = j <= lane ? a[c] : 0.0;
     }
     // lane i of the wave owning column i holds that pivot's reciprocal
-    if (lane >= PW * w && lane < PW * w + PW) rdiag[(int64_t)slot * TB + lane] = myrinv;
+    if (lane >= PW * w && lane < PW * w + PW) {
+        rdiag[(int64_t)slot * TB + lane] = myrinv;
+        if (LDL && lane < kb) dval[p0 + lane] = myd;
+    }
     __syncthreads();
     if (threadIdx.x == 0 && *badmin < INT_MAX) atomicMin(&status[s], p0 + *badmin);
 }
 
 // Diagonal blocks of the first blocked step of each front (later steps factor theirs inside the
 // trailing update of the step before, see blk_syrk).
+template <bool LDL>
 __global__ __launch_bounds__(NT) void blk_potrf(const int32_t* __restrict__ it, const int32_t* __restrict__ first,
                                                 const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
                                                 const int64_t* __restrict__ foff, double* __restrict__ fronts,
                                                 double* __restrict__ ldiag, double* __restrict__ rdiag,
-                                                int32_t* __restrict__ status, PivotRef pr) {
+                                                int32_t* __restrict__ status, PivotRef pr, double* __restrict__ dval) {
     __shared__ __attribute__((aligned(16))) double colbuf[TB * TB];
+    __shared__ double cinv[LDL ? TB : 1];
     __shared__ int flags[2];
     const int s = it[2 * blockIdx.x], k0 = it[2 * blockIdx.x + 1];
-    potrf_block(s, k0, blockIdx.x, first, ncol, mrows, foff, fronts, ldiag, rdiag, status,
-                block_threshold(s, k0, first, ncol, pr), colbuf, flags);
+    potrf_block<LDL>(s, k0, blockIdx.x, first, ncol, mrows, foff, fronts, ldiag, rdiag, status,
+                     block_threshold(s, k0, first, ncol, pr), colbuf, flags, cinv, dval);
 }
 
 constexpr int TR = 64;  // panel rows per work-group of the panel solve
@@ -471,6 +529,9 @@ typedef double double4_t __attribute__((ext_vector_type(4)));
 // row lane % 16 and columns lane / 16 + 4 r of a 16 x 16 block: that is both the accumulator layout and
 // the B-operand layout, so the solved blocks feed the later updates straight from registers, and the
 // stores put 16 consecutive rows of a column on each 16-lane group.
+// LDL: L_D has a unit diagonal and rdiag holds the pivots' reciprocals: the rows are solved with the unit
+// triangle and then scaled column by column, X <- X L_D^{-T} D^{-1}.
+template <bool LDL>
 __global__ __launch_bounds__(NT) void blk_trsm_mma(const int32_t* __restrict__ it, const int32_t* __restrict__ ncol,
                                                    const int32_t* __restrict__ mrows,
                                                    const int64_t* __restrict__ foff, const double* __restrict__ ldiag,
@@ -491,7 +552,7 @@ __global__ __launch_bounds__(NT) void blk_trsm_mma(const int32_t* __restrict__ i
         const int b = wave, q = li;  // the four 16-lane groups compute the same columns; group 0 stores
 #pragma unroll
         for (int r = 0; r < 4; r++) dg[b][4 * r + lk][li] = Lc[(16 * b + li) + TB * (16 * b + 4 * r + lk)];
-        const double rp = lane < 16 ? rc[16 * b + lane] : 0.0;
+        const double rp = lane < 16 ? (LDL ? 1.0 : rc[16 * b + lane]) : 0.0;
         double y[16];
 #pragma unroll
         for (int p = 0; p < 16; p++) {
@@ -536,7 +597,7 @@ __global__ __launch_bounds__(NT) void blk_trsm_mma(const int32_t* __restrict__ i
 #pragma unroll
             for (int r = 0; r < 4; r++) {
                 const int j = 16 * b + lk + 4 * r;
-                if (j < kb) X[ld * j] = y[b][r];
+                if (j < kb) X[ld * j] = LDL ? y[b][r] * rc[j] : y[b][r];
             }
 }
 constexpr int KC = 16;
@@ -555,7 +616,9 @@ constexpr int KH = 16;  // panel columns staged in LDS at a time
 // (128 / 16 RB) x (cw / 16 CB); Pi, Pj hold the negated row panel and the column panel (64 columns,
 // zero past kb).  RB = CB = 4 for 128 x 128 tiles (2 x 2 waves), RB = 2, CB = 4 for the 128 x 64 tiles
 // of the next panel (4 x 1 waves, so the next panel's diagonal block is spread over two waves).
-template <int RB, int CB>
+// LDL: the row panel is scaled by the pivots on its way into LDS (each column's pivot is on the front's
+// diagonal), so the update is C - (Pi D) Pj^T.
+template <int RB, int CB, bool LDL>
 __device__ __forceinline__ void tile_mma(double* __restrict__ F, int m, int ri0, int rj0, int nri, int nrj, int k0,
                                          int kb, double* lds) {
     const double(*Pi)[ST + 1] = reinterpret_cast<const double(*)[ST + 1]>(lds);
@@ -611,6 +674,7 @@ __device__ __forceinline__ void tile_mma(double* __restrict__ F, int m, int ri0,
             const int64_t col = cb + ld * t;
             fa[q] = (in && r < nri) ? F[(int64_t)(ri0 + r) + col] : 0.0;
             fb[q] = (in && r < nrj) ? F[(int64_t)(rj0 + r) + col] : 0.0;
+            if constexpr (LDL) fa[q] *= in ? F[col + (k0 + h0 + t)] : 0.0;
         }
     };
     fetch(0);
@@ -671,19 +735,21 @@ __device__ __forceinline__ void tile_mma(double* __restrict__ F, int m, int ri0,
 // a front's next-panel diagonal tile goes on to factor that panel's diagonal block, which it has just
 // brought up to date, into ldiag slot pslot[item] (-1: no such block), while the other work-groups are
 // still updating the rest: the diagonal-block Cholesky of step k+1 hides under the update of step k.
+template <bool LDL>
 __global__ __launch_bounds__(NT, 2) void blk_syrk(const int32_t* __restrict__ it, int nitems, int nnext, int kw,
                                                const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
                                                const int64_t* __restrict__ foff, double* __restrict__ fronts,
                                                const int32_t* __restrict__ pslot,
                                                const int32_t* __restrict__ first, double* __restrict__ ldiag,
                                                double* __restrict__ rdiag, int32_t* __restrict__ status,
-                                               PivotRef pr) {
+                                               PivotRef pr, double* __restrict__ dval) {
     // LDS: both panel slices of the tile, KH columns at a time (66 KB, so two work-groups share a compute
     // unit and one's loads overlap the other's MFMAs), reused by the fused diagonal-block Cholesky as its
     // 64 x 64 column buffer
     __shared__ __attribute__((aligned(16))) double lds[2 * KH * (ST + 1)];
     static_assert(2 * KH * (ST + 1) >= TB * TB, "the column buffer of the diagonal-block Cholesky fits");
     __shared__ int flags[2];
+    __shared__ double cinv[LDL ? TB : 1];
     for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
         const int s = it[4 * item], k0 = it[4 * item + 1];
         const int ri0 = it[4 * item + 2], rj0 = it[4 * item + 3];
@@ -694,12 +760,13 @@ __global__ __launch_bounds__(NT, 2) void blk_syrk(const int32_t* __restrict__ it
         const int ps = pslot ? pslot[item] : -1;
         const double thr = ps >= 0 ? block_threshold(s, rj0, first, ncol, pr) : 0.0;  // loaded before the tile
         if (item < nnext)
-            tile_mma<2, 4>(F, m, ri0, rj0, nri, min(TB, m - rj0), k0, kb, lds);
+            tile_mma<2, 4, LDL>(F, m, ri0, rj0, nri, min(TB, m - rj0), k0, kb, lds);
         else
-            tile_mma<4, 4>(F, m, ri0, rj0, nri, min(ST, m - rj0), k0, kb, lds);
+            tile_mma<4, 4, LDL>(F, m, ri0, rj0, nri, min(ST, m - rj0), k0, kb, lds);
         if (ps >= 0) {
             __syncthreads();  // the tile's stores are visible to the whole work-group; LDS is free
-            potrf_block(s, rj0, ps, first, ncol, mrows, foff, fronts, ldiag, rdiag, status, thr, lds, flags);
+            potrf_block<LDL>(s, rj0, ps, first, ncol, mrows, foff, fronts, ldiag, rdiag, status, thr, lds, flags,
+                             cinv, dval);
         }
     }
 }
@@ -888,8 +955,8 @@ __global__ __launch_bounds__(NT, 2) void dense_front(int64_t t0, int64_t t1, Den
                             if (i < nri && j < nrj && i >= j) F[fcol(m, rj0 + j) + (ri0 + i)] = acc[a][b][r];
                         }
             __syncthreads();  // the tile's stores are visible to the work-group; LDS is free
-            potrf_block(s, rj0, slot, first, ncol, mrows, foff, fronts, D.tdiag, D.trdiag, status,
-                        block_threshold(s, rj0, first, ncol, pr), Pa, flags);
+            potrf_block<false>(s, rj0, slot, first, ncol, mrows, foff, fronts, D.tdiag, D.trdiag, status,
+                               block_threshold(s, rj0, first, ncol, pr), Pa, flags, nullptr, nullptr);
             publish_final(myflag, epoch);
             continue;
         }
@@ -1005,7 +1072,8 @@ __global__ __launch_bounds__(NT) void solve_fwd(const int32_t* __restrict__ list
                                                 const int64_t* __restrict__ uoff, const int64_t* __restrict__ gptr,
                                                 const int64_t* __restrict__ gsrc,
                                                 const double* __restrict__ fronts, double* __restrict__ work,
-                                                double* __restrict__ upd, double* __restrict__ y, int wcap) {
+                                                double* __restrict__ upd, double* __restrict__ y, int wcap,
+                                                int unit) {
     extern __shared__ double wl[];
     const int s = list[blockIdx.x];
     const int m = mrows[s], nn = ncol[s], f = first[s];
@@ -1035,7 +1103,7 @@ __global__ __launch_bounds__(NT) void solve_fwd(const int32_t* __restrict__ list
 #pragma unroll
             for (int t = 0; t < SCB; t++) a[t] = (act && t < lane) ? Lb[(j0 + lane) + ld * t] : 0.0;
             double wp = act ? w[j0 + lane] : 0.0;
-            const double rp = act ? 1.0 / Lb[(j0 + lane) + ld * lane] : 1.0;
+            const double rp = act && !unit ? 1.0 / Lb[(j0 + lane) + ld * lane] : 1.0;
 #pragma unroll
             for (int t = 0; t < SCB; t++) {
                 const double z = lane_value(wp, t) * lane_value(rp, t);
@@ -1113,7 +1181,7 @@ __global__ __launch_bounds__(NT) void solve_bwd(const int32_t* __restrict__ list
                                                 const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
                                                 const int64_t* __restrict__ foff, const int64_t* __restrict__ roff,
                                                 const int32_t* __restrict__ rows, const double* __restrict__ fronts,
-                                                double* __restrict__ work, double* __restrict__ y) {
+                                                double* __restrict__ work, double* __restrict__ y, int unit) {
     __shared__ double xb[XCH];
     const int s = list[blockIdx.x];
     const int m = mrows[s], nn = ncol[s], f = first[s];
@@ -1169,7 +1237,7 @@ __global__ __launch_bounds__(NT) void solve_bwd(const int32_t* __restrict__ list
 #pragma unroll
             for (int t = 0; t < SCB; t++) a[t] = (act && t > ln && t < cb) ? Lq[j0 + t] : 0.0;
             double wq = act ? w[j0 + ln] : 0.0;
-            const double rq = act ? 1.0 / Lq[j0 + ln] : 1.0;
+            const double rq = act && !unit ? 1.0 / Lq[j0 + ln] : 1.0;
 #pragma unroll
             for (int t = SCB - 1; t >= 0; t--) {
                 if (t >= cb) continue;
@@ -1357,7 +1425,7 @@ __global__ __launch_bounds__(64) void wide_inverse(const int32_t* __restrict__ i
                                                    const int32_t* __restrict__ ncol,
                                                    const int32_t* __restrict__ mrows,
                                                    const int64_t* __restrict__ foff, const double* __restrict__ fronts,
-                                                   double* __restrict__ winv) {
+                                                   double* __restrict__ winv, int unit) {
     __shared__ __attribute__((aligned(16))) double Ls[SB * SB];  // Ls[i * 64 + k] = L(i, k) of the block
     __shared__ double ri[SB];
     const int s = items[3 * blockIdx.x], g = items[3 * blockIdx.x + 1];
@@ -1370,7 +1438,7 @@ __global__ __launch_bounds__(64) void wide_inverse(const int32_t* __restrict__ i
     for (int k = 0; k < SB; k++)
         Ls[j * SB + k] = (j < nb && k < nb) ? (j >= k ? L[j + ld * k] : 0.0) : (j == k ? 1.0 : 0.0);
     __syncthreads();
-    ri[j] = 1.0 / Ls[j * SB + j];
+    ri[j] = unit ? 1.0 : 1.0 / Ls[j * SB + j];
     __syncthreads();
     // row i of L is contiguous in LDS (pairs of broadcasts per read); two partial sums per row
     double x[SB];
@@ -1534,6 +1602,29 @@ __global__ __launch_bounds__(NT) void wide_bwd(int s, double* __restrict__ zx, i
     const double u = (p0 + p1) + (p2 + p3);
     store_coherent(zx + SB * b + j, colok ? u : 0.0);
     if (colok) y[f + c0 + j] = u;
+}
+
+// L D L^T solves: y <- D^{-1} y between the forward and the backward sweep.
+__global__ void dscale(int n, const double* __restrict__ dval, double* __restrict__ y) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) y[k] = y[k] / dval[k];
+}
+
+// Number of negative pivots of an L D L^T factorization (by Sylvester's law of inertia, the number of negative
+// eigenvalues of K when no pivot was rejected), one work-group.
+constexpr int CNT_NT = 1024;
+__global__ __launch_bounds__(CNT_NT) void count_negative(int n, const double* __restrict__ dval,
+                                                         int64_t* __restrict__ out) {
+    __shared__ int64_t red[CNT_NT / 64];
+    int64_t c = 0;
+    for (int k = threadIdx.x; k < n; k += CNT_NT) c += dval[k] < 0.0;
+    for (int o = 32; o > 0; o >>= 1) c += (int64_t)__shfl_xor((long long)c, o);
+    if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < CNT_NT / 64; w++) c += red[w];
+        out[0] = c;
+    }
 }
 
 }  // namespace
@@ -2031,7 +2122,8 @@ static void build_numeric_plan(chol_sym* C, const std::vector<int32_t>& colptr, 
     C->dev.upload(C->winv_it, wit.empty() ? std::vector<int32_t>(3, 0) : wit);
     C->dev.upload(C->sfault, std::vector<int32_t>(1, 0));
     C->dev.upload(C->level_d, C->h_level);
-    C->dev.alloc(C->statwords, 1);
+    C->dev.alloc(C->statwords, 2);
+    C->dev.alloc(C->dval, C->opts.ldlt ? std::max(n, 1) : 1);
 }
 
 extern "C" void chol_default_options(chol_options* o) {
@@ -2044,6 +2136,7 @@ extern "C" void chol_default_options(chol_options* o) {
     o->tile_min = 0;
     o->pair_min = 2048;
     o->pair_panels = 2;
+    o->ldlt = 0;
 }
 
 extern "C" int chol_analyze(int32_t n, const int32_t* colptr, const int32_t* rowind, const chol_options* opts,
@@ -2068,6 +2161,9 @@ extern "C" int chol_analyze(int32_t n, const int32_t* colptr, const int32_t* row
         chol_options o;
         chol_default_options(&o);
         if (opts) o = *opts;
+        OPF_CHECK(o.ldlt == 0 || o.ldlt == 1, OPF_E_INVALID, "chol_analyze: ldlt must be 0 or 1");
+        OPF_CHECK(!(o.ldlt && o.tile_min > 0), OPF_E_INVALID,
+                  "chol_analyze: the dependency-driven tile path (tile_min > 0) factors by Cholesky only");
         auto* C = new chol_sym();
         try {
             C->opts = o;
@@ -2241,6 +2337,7 @@ void chol_factor_enqueue(chol_sym* C, const double* kval, hipStream_t st, double
     chol_set_stream(C, st);  // first use: the uploads go on the caller's stream
     C->dev.run();
     const PivotRef pr{kval, C->kdiagpos.p, pivot_tol};
+    const bool ldl = C->opts.ldlt != 0;
     C->epoch++;
     hipLaunchKernelGGL(reset_words, dim3(1), dim3(64), 0, st, C->ffault.p, (int32_t*)nullptr);
     OPF_LAUNCH_CHECK();
@@ -2259,8 +2356,9 @@ void chol_factor_enqueue(chol_sym* C, const double* kval, hipStream_t st, double
         int s0 = C->lvl_small_ptr[l], s1 = C->lvl_small_ptr[l + 1];
         if (s1 > s0) {
             tmark(C, st, 1);
-            hipLaunchKernelGGL(front_small, dim3(s1 - s0), dim3(NT), 0, st, C->lvl_small_d.p + s0, C->first.p,
-                               C->ncol.p, C->mrows.p, C->foff.p, C->fronts.p, C->status.p, pr);
+            hipLaunchKernelGGL(ldl ? front_small<true> : front_small<false>, dim3(s1 - s0), dim3(NT), 0, st,
+                               C->lvl_small_d.p + s0, C->first.p, C->ncol.p, C->mrows.p, C->foff.p, C->fronts.p,
+                               C->status.p, pr, C->dval.p);
             OPF_LAUNCH_CHECK();
             tmark(C, st, 1);
         }
@@ -2281,24 +2379,26 @@ void chol_factor_enqueue(chol_sym* C, const double* kval, hipStream_t st, double
             const chol_sym::Step& S = C->steps[q];
             if (q == q0 && S.p1 > S.p0) {  // later steps factor their diagonal blocks in the update before
                 tmark(C, st, 2);
-                hipLaunchKernelGGL(blk_potrf, dim3(S.p1 - S.p0), dim3(NT), 0, st, C->potrf_it.p + 2 * S.p0,
-                                   C->first.p, C->ncol.p, C->mrows.p, C->foff.p, C->fronts.p, C->ldiag.p,
-                                   C->rdiag.p, C->status.p, pr);
+                hipLaunchKernelGGL(ldl ? blk_potrf<true> : blk_potrf<false>, dim3(S.p1 - S.p0), dim3(NT), 0, st,
+                                   C->potrf_it.p + 2 * S.p0, C->first.p, C->ncol.p, C->mrows.p, C->foff.p,
+                                   C->fronts.p, C->ldiag.p, C->rdiag.p, C->status.p, pr, C->dval.p);
                 OPF_LAUNCH_CHECK();
                 tmark(C, st, 2);
             }
             if (S.t1 > S.t0) {
                 tmark(C, st, 3);
-                hipLaunchKernelGGL(blk_trsm_mma, dim3(S.t1 - S.t0), dim3(NT), 0, st, C->trsm_it.p + 4 * S.t0,
-                                   C->ncol.p, C->mrows.p, C->foff.p, C->ldiag.p, C->rdiag.p, C->fronts.p);
+                hipLaunchKernelGGL(ldl ? blk_trsm_mma<true> : blk_trsm_mma<false>, dim3(S.t1 - S.t0), dim3(NT), 0, st,
+                                   C->trsm_it.p + 4 * S.t0, C->ncol.p, C->mrows.p, C->foff.p, C->ldiag.p, C->rdiag.p,
+                                   C->fronts.p);
                 OPF_LAUNCH_CHECK();
                 tmark(C, st, 3);
             }
             if (S.r1 > S.s0) {
                 tmark(C, st, 4);
-                hipLaunchKernelGGL(blk_syrk, dim3(S.r1 - S.s0), dim3(NT), 0, st, C->syrk_it.p + 4 * S.s0, S.r1 - S.s0,
-                                   S.s1 - S.s0, S.kw, C->ncol.p, C->mrows.p, C->foff.p, C->fronts.p, C->next_slot.p + S.s0,
-                                   C->first.p, C->ldiag.p, C->rdiag.p, C->status.p, pr);
+                hipLaunchKernelGGL(ldl ? blk_syrk<true> : blk_syrk<false>, dim3(S.r1 - S.s0), dim3(NT), 0, st,
+                                   C->syrk_it.p + 4 * S.s0, S.r1 - S.s0, S.s1 - S.s0, S.kw, C->ncol.p, C->mrows.p,
+                                   C->foff.p, C->fronts.p, C->next_slot.p + S.s0, C->first.p, C->ldiag.p, C->rdiag.p,
+                                   C->status.p, pr, C->dval.p);
                 OPF_LAUNCH_CHECK();
                 tmark(C, st, 4);
             }
@@ -2310,7 +2410,11 @@ void chol_factor_enqueue(chol_sym* C, const double* kval, hipStream_t st, double
     }
     if (C->nwinv > 0) {  // diagonal-block inverses of the wide fronts for the sweeps
         hipLaunchKernelGGL(wide_inverse, dim3(C->nwinv), dim3(64), 0, st, C->winv_it.p, C->ncol.p, C->mrows.p,
-                           C->foff.p, C->fronts.p, C->winv.p);
+                           C->foff.p, C->fronts.p, C->winv.p, (int)ldl);
+        OPF_LAUNCH_CHECK();
+    }
+    if (ldl) {
+        hipLaunchKernelGGL(count_negative, dim3(1), dim3(CNT_NT), 0, st, C->n, C->dval.p, C->statwords.p + 1);
         OPF_LAUNCH_CHECK();
     }
 }
@@ -2362,7 +2466,9 @@ int chol_factor_sync(chol_sym* C, const double* kval, hipStream_t st, double piv
     hw[1] = 0;  // the fault word fills its low half
     OPF_HIP(hipMemcpyAsync(hw, C->statwords.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     OPF_HIP(hipMemcpyAsync(hw + 1, C->ffault.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    if (C->opts.ldlt) OPF_HIP(hipMemcpyAsync(hw + 3, C->statwords.p + 1, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     OPF_HIP(hipStreamSynchronize(st));
+    C->last_nneg = C->opts.ldlt ? hw[3] : 0;
     tcollect(C);
     const int64_t key = hw[0];
     const int32_t ffault = (int32_t)hw[1];
@@ -2393,7 +2499,7 @@ static void solve_enqueue(chol_sym* C, const double* b, double* x, hipStream_t s
             const int wcap = std::min(C->lvl_narrow_maxm[l], WLDS);  // fronts up to wcap rows keep w in LDS
             hipLaunchKernelGGL(solve_fwd, dim3(q1 - q0), dim3(NT), (size_t)wcap * sizeof(double), st,
                                C->lvl_narrow_d.p + q0, C->first.p, C->ncol.p, C->mrows.p, C->foff.p, C->roff.p,
-                               C->uoff.p, C->gptr.p, C->gsrc.p, C->fronts.p, B.work, B.upd, y, wcap);
+                               C->uoff.p, C->gptr.p, C->gsrc.p, C->fronts.p, B.work, B.upd, y, wcap, C->opts.ldlt);
             OPF_LAUNCH_CHECK();
             const int t0 = C->lvl_trow_ptr[l], t1 = C->lvl_trow_ptr[l + 1];
             if (t1 > t0) {  // the tall fronts' rows below their pivots
@@ -2423,6 +2529,10 @@ static void solve_enqueue(chol_sym* C, const double* b, double* x, hipStream_t s
             }
         }
     }
+    if (C->opts.ldlt) {  // L D L^T: the forward sweeps solved with the unit triangle; now D
+        hipLaunchKernelGGL(dscale, dim3(ceil_div(n, 256)), dim3(256), 0, st, n, C->dval.p, y);
+        OPF_LAUNCH_CHECK();
+    }
     for (int l = C->nlevels - 1; l >= 0; l--) {
         int w0 = C->lvl_wide_ptr[l], w1 = C->lvl_wide_ptr[l + 1];
         for (int q = w0; q < w1; q++) {
@@ -2446,7 +2556,8 @@ static void solve_enqueue(chol_sym* C, const double* b, double* x, hipStream_t s
         }
         if (q1 > q0) {
             hipLaunchKernelGGL(solve_bwd, dim3(q1 - q0), dim3(NT), 0, st, C->lvl_narrow_d.p + q0, C->first.p,
-                               C->ncol.p, C->mrows.p, C->foff.p, C->roff.p, C->rows.p, C->fronts.p, B.work, y);
+                               C->ncol.p, C->mrows.p, C->foff.p, C->roff.p, C->rows.p, C->fronts.p, B.work, y,
+                               C->opts.ldlt);
             OPF_LAUNCH_CHECK();
         }
     }
@@ -2484,6 +2595,9 @@ static int read_fault(const chol_sym* C, const int32_t* fault, hipStream_t st) {
 
 int chol_solve_fault(chol_sym* C, hipStream_t st) { return read_fault(C, C->sfault.p, st); }
 
+// Negative pivots of the last factorization (0 for Cholesky).
+int64_t chol_last_negative(const chol_sym* C) { return C->last_nneg; }
+
 // Pending device uploads of the analysis run on st (when they have not run yet).
 void chol_set_stream(chol_sym* C, hipStream_t st) {
     if (!C->dev.done) C->dev.stream = st;
@@ -2517,9 +2631,20 @@ extern "C" int chol_factor(chol_sym* C, const double* kval, void* stream, int32_
         int bad = chol_factor_sync(C, kval, (hipStream_t)stream, C->opts.pivot_tol);
         if (bad_col) *bad_col = bad;
         if (bad >= 0) {
-            set_error("chol_factor: non-positive pivot at pivot index %d", bad);
+            set_error(C->opts.ldlt ? "chol_factor: zero (or below tolerance) pivot at pivot index %d"
+                                   : "chol_factor: non-positive pivot at pivot index %d",
+                      bad);
             throw Error{OPF_E_NOT_PD};
         }
+    });
+}
+
+extern "C" int chol_inertia(const chol_sym* C, int64_t* npos, int64_t* nneg) {
+    return guarded([&] {
+        OPF_CHECK(C && npos && nneg, OPF_E_INVALID, "chol_inertia: null argument");
+        OPF_CHECK(C->factored, OPF_E_STATE, "chol_inertia: no successful factorization");
+        *nneg = C->last_nneg;
+        *npos = C->n - C->last_nneg;
     });
 }
 

@@ -24,6 +24,7 @@
 namespace opf {
 void chol_factor_enqueue(chol_sym* C, const double* kval, hipStream_t st, double pivot_tol);
 int chol_factor_sync(chol_sym* C, const double* kval, hipStream_t st, double pivot_tol);
+int64_t chol_last_negative(const chol_sym* C);
 void chol_solve_enqueue(chol_sym* C, const double* b, double* x, hipStream_t st);
 int chol_solve_fault(chol_sym* C, hipStream_t st);
 void chol_prepare_device(chol_sym* C);
@@ -834,7 +835,9 @@ static int compute_direction(ipm_state* S, double mu, ipm_iter_info& I) {
         t_asm += a;
         t_fac += b;
         I.factorizations++;
-        return bad < 0;
+        // the condensed matrix must be positive definite (Section IV-C); an L D L^T factorization reports it
+        // through the signs of its pivots (zero pivots are rejected like non-positive Cholesky pivots)
+        return bad < 0 && chol_last_negative(S->C) == 0;
     };
     double dw = 0.0;
     if (!try_factor(0.0)) {

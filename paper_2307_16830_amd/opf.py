@@ -28,7 +28,7 @@ EXPORTED = [
     "opf_last_error", "opf_default_options", "opf_create", "opf_destroy", "opf_dims", "opf_structure", "opf_bounds", "opf_initial_point",
     "opf_eval_derivs", "kkt_pattern", "kkt_condense", "chol_default_options", "chol_analyze", "chol_destroy",
     "chol_info", "chol_perm", "chol_etree", "chol_supernodes", "chol_supernode_rows", "chol_factor", "chol_solve",
-    "chol_solve_noalloc", "chol_graph_stats",
+    "chol_solve_noalloc", "chol_graph_stats", "chol_inertia",
     "chol_export_factor", "ipm_default_options", "ipm_create", "ipm_destroy", "ipm_step", "ipm_solve",
     "ipm_get_iterate", "ipm_chol", "ipm_get_state", "ipm_set_state", "ipm_direction", "chol_timing",
     "chol_timing_read", "serve_default_options", "opf_serve_create", "opf_serve_submit", "opf_serve_poll",
@@ -68,7 +68,8 @@ class IpmResult(ctypes.Structure):
 class CholOptions(ctypes.Structure):
     _fields_ = [("dense_frac", ctypes.c_double), ("dense_abs", ctypes.c_int32), ("max_width", ctypes.c_int32),
                 ("zero_abs", ctypes.c_int64), ("zero_rel", ctypes.c_double), ("pivot_tol", ctypes.c_double),
-                ("tile_min", ctypes.c_int32), ("pair_min", ctypes.c_int32), ("pair_panels", ctypes.c_int32)]
+                ("tile_min", ctypes.c_int32), ("pair_min", ctypes.c_int32), ("pair_panels", ctypes.c_int32),
+                ("ldlt", ctypes.c_int32)]
 
 
 class IpmOptions(ctypes.Structure):
@@ -140,6 +141,7 @@ def lib():
         L.chol_solve.argtypes = [VP, VP, VP, ctypes.c_int32, VP]
         L.chol_solve_noalloc.argtypes = [VP, VP, VP, ctypes.c_int32, VP]
         L.chol_graph_stats.argtypes = [ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+        L.chol_inertia.argtypes = [VP, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
         L.chol_export_factor.argtypes = [VP, I64P, I32P, F64P]
         L.chol_timing.argtypes = [VP, ctypes.c_int]
         L.chol_timing_read.argtypes = [VP, F64P, I64P, F64P, F64P]
@@ -348,13 +350,20 @@ class Cholesky:
         return rp, rows
 
     def factor(self, kval, stream=None):
-        """Returns -1 when positive definite, else the failing pivot index (no exception)."""
+        """Returns -1 when every pivot was accepted (Cholesky: K positive definite; ``ldlt``: no zero pivot), else
+        the failing pivot index (no exception)."""
         bad = ctypes.c_int32(-1)
         rc = lib().chol_factor(self._h, _dptr(kval), _stream(stream), ctypes.byref(bad))
         if rc == E_NOT_PD:
             return bad.value
         _check(rc, "chol_factor")
         return -1
+
+    def inertia(self):
+        """(positive, negative) pivot counts of the last successful factorization (``chol_inertia``)."""
+        p, q = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().chol_inertia(self._h, ctypes.byref(p), ctypes.byref(q)), "chol_inertia")
+        return p.value, q.value
 
     def solve(self, b, x=None, stream=None):
         if x is None:
