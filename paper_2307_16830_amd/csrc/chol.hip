@@ -1025,10 +1025,6 @@ __global__ __launch_bounds__(NT, 2) void dense_front(int64_t t0, int64_t t1, Den
     }
 }
 
-__global__ void reset_counter(int32_t* c) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0;
-}
-
 // ---------------------------------------------------------------- solves
 __global__ void permute_in(int n, const int32_t* __restrict__ perm, const double* __restrict__ b,
                            double* __restrict__ y) {

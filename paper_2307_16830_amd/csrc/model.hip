@@ -113,6 +113,11 @@ __global__ __launch_bounds__(AD_BLOCK) void ad_templates(AdParams P) {
         // ---------------- arc template: patterns 3-6 (flows), 8-9 (thermal), 7 (angle on a < E)
         int a = b * AD_BLOCK + threadIdx.x;
         if (a >= A) return;
+        if (wg) {  // the gradient has no arc-flow terms
+            P.grad[op + a] = 0.0;
+            P.grad[oq + a] = 0.0;
+        }
+        if (!(wc || wj || wh)) return;
         const int i = P.ai[a], j = P.aj[a];
         const double g = P.ag[a], bb = P.ab[a], bc = P.abc[a];
         const double vai = P.x[ova + i], vaj = P.x[ova + j];
@@ -188,6 +193,11 @@ __global__ __launch_bounds__(AD_BLOCK) void ad_templates(AdParams P) {
         // ---------------- bus template: patterns 10-15 (balances with arc and generator gathers), 2 (ref)
         int i = b * AD_BLOCK + threadIdx.x;
         if (i >= N) return;
+        if (wg) {  // nor voltage terms
+            P.grad[ova + i] = 0.0;
+            P.grad[ovm + i] = 0.0;
+        }
+        if (!(wc || wj || wh)) return;
         const double vm = P.x[ovm + i];
         const int64_t rpb = R.pb + i, rqb = R.qb + i;
         const double spb = rs(P.cscale, rpb), sqb = rs(P.cscale, rqb);
@@ -230,23 +240,16 @@ __global__ __launch_bounds__(AD_BLOCK) void ad_templates(AdParams P) {
         if (k >= G) return;
         const double pg = P.x[opg + k];
         const Jet<1> f = cost(Jet<1>::input(pg, 0), P.c2[k], P.c1[k]);
-        if (wg) P.grad[opg + k] = P.gscale * f.g[0];
+        if (wg) {
+            P.grad[opg + k] = P.gscale * f.g[0];
+            P.grad[oqg + k] = 0.0;
+        }
         if (wjc) {
             const int i = P.gbus[k];
             P.jac[JL.bal_pg + k] = -rs(P.cscale, R.pb + i);
             P.jac[JL.bal_qg + k] = -rs(P.cscale, R.qb + i);
         }
         if (wh) P.hess[HL.gen + k] = P.obj_weight * f.h[0];
-        return;
-    }
-    b -= P.gen_blocks;
-    // ---------------- zero the gradient outside the pg block
-    if (wg) {
-        int64_t v = (int64_t)b * AD_BLOCK + threadIdx.x;
-        int64_t nz = (int64_t)P.N * 2 + ((int64_t)2 * G + 4LL * E - G);
-        if (v >= nz) return;
-        int64_t idx = v < 2LL * N ? v : v + G;
-        P.grad[idx] = 0.0;
     }
 }
 
@@ -305,11 +308,11 @@ void eval_derivs(const opf_model* M, unsigned what, const double* x, const doubl
     P.hess = hess;
     unsigned tmpl = what & (OPF_EVAL_C | OPF_EVAL_GRAD | OPF_EVAL_JAC | OPF_EVAL_HESS);
     if (tmpl) {
-        P.arc_blocks = (what & (OPF_EVAL_C | OPF_EVAL_JAC | OPF_EVAL_HESS)) ? ceil_div(2LL * M->E, AD_BLOCK) : 0;
-        P.bus_blocks = (what & (OPF_EVAL_C | OPF_EVAL_JAC | OPF_EVAL_HESS)) ? ceil_div(M->N, AD_BLOCK) : 0;
+        // the arc and bus threads also zero their gradient entries (the gradient is the cost's, on pg only)
+        P.arc_blocks = ceil_div(2LL * M->E, AD_BLOCK);
+        P.bus_blocks = ceil_div(M->N, AD_BLOCK);
         P.gen_blocks = ceil_div(M->G, AD_BLOCK);
-        int zero_blocks = (what & OPF_EVAL_GRAD) ? ceil_div((size_t)M->n - M->G, AD_BLOCK) : 0;
-        int nb = P.arc_blocks + P.bus_blocks + P.gen_blocks + zero_blocks;
+        int nb = P.arc_blocks + P.bus_blocks + P.gen_blocks;
         if (nb > 0) {
             hipLaunchKernelGGL(ad_templates, dim3(nb), dim3(AD_BLOCK), 0, s, P);
             OPF_LAUNCH_CHECK();
