@@ -546,13 +546,45 @@ __global__ __launch_bounds__(NT) void blk_trsm_mma(const int32_t* __restrict__ i
     const double* rc = rdiag + (int64_t)slot * TB;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
     const int li = lane % 16, lk = lane / 16;
+    const int row = k0 + kb + rb * TR + 16 * wave + li;
+    const bool rowok = row < m;
+    const int64_t ld = fld(m, k0);
+    double* X = fronts + foff[s] + fcol(m, k0) + (rowok ? row : 0);  // X[ld j] = entry (row, k0 + j)
+    // Every global load of the kernel is issued here, before the diagonal blocks are inverted: the wave's
+    // diagonal block (rows of a column are contiguous), the reciprocal pivots, the rows' 64 entries and the
+    // off-diagonal 16 x 16 blocks of L_D that the substitution's MFMAs take (lof[b (b - 1) / 2 + a] for a < b),
+    // so that their latency overlaps the inversion instead of sitting between the substitution's stages.
+    double dgv[4];
+#pragma unroll
+    for (int r = 0; r < 4; r++) dgv[r] = Lc[(16 * wave + li) + TB * (16 * wave + 4 * r + lk)];
+    const double rp = lane < 16 ? (LDL ? 1.0 : rc[16 * wave + lane]) : 0.0;
+    double4_t xin[4];
+#pragma unroll
+    for (int b = 0; b < 4; b++)
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int j = 16 * b + lk + 4 * r;
+            xin[b][r] = (rowok && j < kb) ? X[ld * j] : 0.0;
+        }
+    double lof[6][4];
+#pragma unroll
+    for (int b = 1; b < 4; b++)
+#pragma unroll
+        for (int a = 0; a < b; a++)
+#pragma unroll
+            for (int kk = 0; kk < 4; kk++) lof[b * (b - 1) / 2 + a][kk] = -Lc[(16 * b + li) + TB * (16 * a + 4 * kk + lk)];
+    double dsc[4][4];  // L D L^T: the pivots' reciprocals for the final column scaling
+    if constexpr (LDL) {
+#pragma unroll
+        for (int b = 0; b < 4; b++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) dsc[b][r] = rc[min(16 * b + lk + 4 * r, kb - 1)];
+    }
     {
-        // the wave's diagonal block into LDS in one round of loads (rows of a column are contiguous), then
-        // the substitution reads it as broadcasts
+        // the wave's diagonal block into LDS, then the inversion reads it as broadcasts
         const int b = wave, q = li;  // the four 16-lane groups compute the same columns; group 0 stores
 #pragma unroll
-        for (int r = 0; r < 4; r++) dg[b][4 * r + lk][li] = Lc[(16 * b + li) + TB * (16 * b + 4 * r + lk)];
-        const double rp = lane < 16 ? (LDL ? 1.0 : rc[16 * b + lane]) : 0.0;
+        for (int r = 0; r < 4; r++) dg[b][4 * r + lk][li] = dgv[r];
         double y[16];
 #pragma unroll
         for (int p = 0; p < 16; p++) {
@@ -565,26 +597,16 @@ __global__ __launch_bounds__(NT) void blk_trsm_mma(const int32_t* __restrict__ i
 #pragma unroll
             for (int p = 0; p < 16; p++) inv[b][p][q] = y[p];
     }
-    const int row = k0 + kb + rb * TR + 16 * wave + li;
-    const bool rowok = row < m;
-    const int64_t ld = fld(m, k0);
-    double* X = fronts + foff[s] + fcol(m, k0) + (rowok ? row : 0);  // X[ld j] = entry (row, k0 + j)
     double4_t y[4];
     __syncthreads();
 #pragma unroll
     for (int b = 0; b < 4; b++) {
-        double4_t acc;
-#pragma unroll
-        for (int r = 0; r < 4; r++) {
-            const int j = 16 * b + lk + 4 * r;
-            acc[r] = (rowok && j < kb) ? X[ld * j] : 0.0;
-        }
+        double4_t acc = xin[b];
 #pragma unroll
         for (int a = 0; a < b; a++)
 #pragma unroll
             for (int kk = 0; kk < 4; kk++)
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-Lc[(16 * b + li) + TB * (16 * a + 4 * kk + lk)], y[a][kk],
-                                                           acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(lof[b * (b - 1) / 2 + a][kk], y[a][kk], acc, 0, 0, 0);
         double4_t out = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int kk = 0; kk < 4; kk++)
@@ -597,7 +619,7 @@ __global__ __launch_bounds__(NT) void blk_trsm_mma(const int32_t* __restrict__ i
 #pragma unroll
             for (int r = 0; r < 4; r++) {
                 const int j = 16 * b + lk + 4 * r;
-                if (j < kb) X[ld * j] = LDL ? y[b][r] * rc[j] : y[b][r];
+                if (j < kb) X[ld * j] = LDL ? y[b][r] * dsc[b][r] : y[b][r];
             }
 }
 constexpr int KC = 16;
