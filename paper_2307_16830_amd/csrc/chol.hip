@@ -55,7 +55,7 @@ struct chol_sym {
     std::vector<int32_t> lvl_ptr, lvl_sn;           // supernodes by level
     std::vector<int32_t> lvl_small_ptr, lvl_small;  // fronts with m <= 64 by level
     std::vector<int32_t> lvl_narrow_ptr, lvl_narrow;  // fronts solved by one work-group, by level
-    std::vector<int32_t> lvl_narrow_maxm;             // largest front of each level's list
+    std::vector<int32_t> lvl_narrow_maxm;             // largest front of each level's list (<= 64: one-wave sweeps)
     // narrow fronts with many rows below their pivots ("tall"): the sweeps' products with those rows run as
     // separate launches over row blocks (forward) and 16-column blocks (backward), items (front, block)
     std::vector<int32_t> lvl_trow_ptr, lvl_tcol_ptr, trow_it, tcol_it;
@@ -1189,6 +1189,102 @@ __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
     return v;
+}
+
+// Sweeps of levels whose fronts all have m <= 64 rows (plain squares): one wave per front and four fronts per
+// work-group, since the leaf levels hold thousands of tiny fronts and a work-group per front costs more to
+// dispatch than its work.  Lane i is on row i; every row gets the same operations in the same order as in
+// solve_fwd / solve_bwd, so the results are theirs bit for bit.
+// Forward: w = b(own rows) + the children's update entries; pivot j: z_j = w_j (1 / L_jj) (unit: L_jj = 1),
+// then w_i -= L_ij z_j below it, the loads of 16 pivots' columns in flight together.
+__global__ __launch_bounds__(NT) void solve_fwd_tiny(int nf, const int32_t* __restrict__ list,
+                                                     const int32_t* __restrict__ first,
+                                                     const int32_t* __restrict__ ncol,
+                                                     const int32_t* __restrict__ mrows,
+                                                     const int64_t* __restrict__ foff, const int64_t* __restrict__ roff,
+                                                     const int64_t* __restrict__ uoff,
+                                                     const int64_t* __restrict__ gptr, const int64_t* __restrict__ gsrc,
+                                                     const double* __restrict__ fronts, double* __restrict__ upd,
+                                                     double* __restrict__ y, int unit) {
+    const int lane = threadIdx.x % 64;
+    const int q = blockIdx.x * (NT / 64) + threadIdx.x / 64;
+    if (q >= nf) return;
+    const int s = list[q];
+    const int m = mrows[s], nn = ncol[s], f = first[s];
+    const bool row = lane < m;
+    const int64_t* gp = gptr + roff[s];
+    const double* L = fronts + foff[s];
+    double w = row ? row_gather(lane < nn ? y[f + lane] : 0.0, gp[lane], gp[lane + 1], gsrc, upd) : 0.0;
+    const double rp = lane < nn && !unit ? 1.0 / L[lane + m * lane] : 1.0;
+    double zl = 0.0;
+    for (int j0 = 0; j0 < nn; j0 += SCB) {
+        double lv[SCB];  // L(lane, j0 + t)
+#pragma unroll
+        for (int t = 0; t < SCB; t++) lv[t] = row && lane > j0 + t && j0 + t < nn ? L[lane + m * (j0 + t)] : 0.0;
+#pragma unroll
+        for (int t = 0; t < SCB; t++) {
+            if (j0 + t < nn) {
+                const double z = lane_value(w, j0 + t) * lane_value(rp, j0 + t);
+                if (lane == j0 + t) zl = z;
+                if (row && lane > j0 + t) w = fma(-lv[t], z, w);
+            }
+        }
+    }
+    if (lane < nn)
+        y[f + lane] = zl;
+    else if (row)
+        upd[uoff[s] + (lane - nn)] = w;
+}
+
+// Backward: w_j = y_j - L(rows below, j)^T x(rows below) (summed across the wave as in solve_bwd: lane t on
+// row nn + t), then the pivots from the last: x_t = w_t (1 / L_tt), w_j -= L_tj x_t for j < t.
+__global__ __launch_bounds__(NT) void solve_bwd_tiny(int nf, const int32_t* __restrict__ list,
+                                                     const int32_t* __restrict__ first,
+                                                     const int32_t* __restrict__ ncol,
+                                                     const int32_t* __restrict__ mrows,
+                                                     const int64_t* __restrict__ foff, const int64_t* __restrict__ roff,
+                                                     const int32_t* __restrict__ rows,
+                                                     const double* __restrict__ fronts, double* __restrict__ y,
+                                                     int unit) {
+    const int lane = threadIdx.x % 64;
+    const int q = blockIdx.x * (NT / 64) + threadIdx.x / 64;
+    if (q >= nf) return;
+    const int s = list[q];
+    const int m = mrows[s], nn = ncol[s], f = first[s];
+    const int32_t* R = rows + roff[s];
+    const double* L = fronts + foff[s];
+    const int nr = m - nn;
+    const double xr = lane < nr ? y[R[nn + lane]] : 0.0;  // solved value of row nn + lane
+    double w = lane < nn ? y[f + lane] : 0.0;
+    for (int j0 = 0; j0 < nn; j0 += SCB) {
+        double lv[SCB];  // L(nn + lane, j0 + t)
+#pragma unroll
+        for (int t = 0; t < SCB; t++) lv[t] = lane < nr && j0 + t < nn ? L[(nn + lane) + m * (j0 + t)] : 0.0;
+#pragma unroll
+        for (int t = 0; t < SCB; t++) {
+            if (j0 + t < nn) {
+                const double acc = wave_sum((lv[t] * xr + 0.0) + (0.0 + 0.0));
+                if (lane == j0 + t) w -= acc;
+            }
+        }
+    }
+    const double rq = lane < nn && !unit ? 1.0 / L[lane + m * lane] : 1.0;
+    double xl = 0.0;
+    for (int j1 = nn; j1 > 0; j1 -= SCB) {
+        double lv[SCB];  // L(j1 - 1 - t, lane)
+#pragma unroll
+        for (int t = 0; t < SCB; t++) lv[t] = j1 - 1 - t >= 0 && lane < j1 - 1 - t ? L[(j1 - 1 - t) + m * lane] : 0.0;
+#pragma unroll
+        for (int t = 0; t < SCB; t++) {
+            const int p = j1 - 1 - t;
+            if (p >= 0) {
+                const double x = lane_value(w, p) * lane_value(rq, p);
+                if (lane == p) xl = x;
+                if (lane < p) w = fma(-lv[t], x, w);
+            }
+        }
+    }
+    if (lane < nn) y[f + lane] = xl;
 }
 
 // Backward sweep for one front: x(own) = L11^{-T} (y(own) - L21^T x(rows below)).  The products with
@@ -2514,10 +2610,17 @@ static void solve_enqueue(chol_sym* C, const double* b, double* x, hipStream_t s
     for (int l = 0; l < C->nlevels; l++) {
         int q0 = C->lvl_narrow_ptr[l], q1 = C->lvl_narrow_ptr[l + 1];
         if (q1 > q0) {
-            const int wcap = std::min(C->lvl_narrow_maxm[l], WLDS);  // fronts up to wcap rows keep w in LDS
-            hipLaunchKernelGGL(solve_fwd, dim3(q1 - q0), dim3(NT), (size_t)wcap * sizeof(double), st,
-                               C->lvl_narrow_d.p + q0, C->first.p, C->ncol.p, C->mrows.p, C->foff.p, C->roff.p,
-                               C->uoff.p, C->gptr.p, C->gsrc.p, C->fronts.p, B.work, B.upd, y, wcap, C->opts.ldlt);
+            if (C->lvl_narrow_maxm[l] <= TB) {  // only fronts of at most 64 rows: four to a work-group
+                hipLaunchKernelGGL(solve_fwd_tiny, dim3(ceil_div(q1 - q0, NT / 64)), dim3(NT), 0, st, q1 - q0,
+                                   C->lvl_narrow_d.p + q0, C->first.p, C->ncol.p, C->mrows.p, C->foff.p, C->roff.p,
+                                   C->uoff.p, C->gptr.p, C->gsrc.p, C->fronts.p, B.upd, y, C->opts.ldlt);
+            } else {
+                const int wcap = std::min(C->lvl_narrow_maxm[l], WLDS);  // fronts up to wcap rows keep w in LDS
+                hipLaunchKernelGGL(solve_fwd, dim3(q1 - q0), dim3(NT), (size_t)wcap * sizeof(double), st,
+                                   C->lvl_narrow_d.p + q0, C->first.p, C->ncol.p, C->mrows.p, C->foff.p, C->roff.p,
+                                   C->uoff.p, C->gptr.p, C->gsrc.p, C->fronts.p, B.work, B.upd, y, wcap,
+                                   C->opts.ldlt);
+            }
             OPF_LAUNCH_CHECK();
             const int t0 = C->lvl_trow_ptr[l], t1 = C->lvl_trow_ptr[l + 1];
             if (t1 > t0) {  // the tall fronts' rows below their pivots
@@ -2573,9 +2676,14 @@ static void solve_enqueue(chol_sym* C, const double* b, double* x, hipStream_t s
             OPF_LAUNCH_CHECK();
         }
         if (q1 > q0) {
-            hipLaunchKernelGGL(solve_bwd, dim3(q1 - q0), dim3(NT), 0, st, C->lvl_narrow_d.p + q0, C->first.p,
-                               C->ncol.p, C->mrows.p, C->foff.p, C->roff.p, C->rows.p, C->fronts.p, B.work, y,
-                               C->opts.ldlt);
+            if (C->lvl_narrow_maxm[l] <= TB)
+                hipLaunchKernelGGL(solve_bwd_tiny, dim3(ceil_div(q1 - q0, NT / 64)), dim3(NT), 0, st, q1 - q0,
+                                   C->lvl_narrow_d.p + q0, C->first.p, C->ncol.p, C->mrows.p, C->foff.p, C->roff.p,
+                                   C->rows.p, C->fronts.p, y, C->opts.ldlt);
+            else
+                hipLaunchKernelGGL(solve_bwd, dim3(q1 - q0), dim3(NT), 0, st, C->lvl_narrow_d.p + q0, C->first.p,
+                                   C->ncol.p, C->mrows.p, C->foff.p, C->roff.p, C->rows.p, C->fronts.p, B.work, y,
+                                   C->opts.ldlt);
             OPF_LAUNCH_CHECK();
         }
     }
