@@ -54,6 +54,7 @@ struct chol_sym {
     std::vector<int64_t> h_foff, h_roff, h_uoff;
     std::vector<int32_t> lvl_ptr, lvl_sn;           // supernodes by level
     std::vector<int32_t> lvl_small_ptr, lvl_small;  // fronts with m <= 64 by level
+    std::vector<int32_t> lvl_small_maxm;            // largest of them, 0 when the level has larger fronts too
     std::vector<int32_t> lvl_narrow_ptr, lvl_narrow;  // fronts solved by one work-group, by level
     std::vector<int32_t> lvl_narrow_maxm;             // largest front of each level's list (<= 64: one-wave sweeps)
     // narrow fronts with many rows below their pivots ("tall"): the sweeps' products with those rows run as
@@ -222,6 +223,59 @@ __global__ __launch_bounds__(NT) void front_assemble(int tile0, const int32_t* _
     for (int e = threadIdx.x; e < TB * TB; e += NT) {
         const int i = r0 + e % TB, j = c0 + e / TB;
         if (i < m && j < m && i >= j) F[i + ld * (j - c0)] = T[e];
+    }
+}
+
+// Assembly of a level whose fronts all have at most 64 rows (one tile each, a plain square): one wave per
+// front and up to `blockDim.x / 64` fronts per work-group, each in its own lda x lda square of dynamic LDS
+// (lda = the level's largest front), the K entries first and then the children in order, as in
+// front_assemble (so the fronts are bit for bit the same); a wave's LDS accesses are performed in order.
+__global__ __launch_bounds__(NT) void front_assemble_tiny(int tile0, int nt, int lda,
+                                                          const int32_t* __restrict__ tile_sn,
+                                                          const int64_t* __restrict__ tile_kptr,
+                                                          const int32_t* __restrict__ tile_k,
+                                                          const int32_t* __restrict__ tile_kpos,
+                                                          const double* __restrict__ kval,
+                                                          const int32_t* __restrict__ ncol,
+                                                          const int32_t* __restrict__ mrows,
+                                                          const int64_t* __restrict__ foff,
+                                                          const int64_t* __restrict__ tile_cptr,
+                                                          const int32_t* __restrict__ tile_crec,
+                                                          const int64_t* __restrict__ rel_off,
+                                                          const int32_t* __restrict__ rel, double* __restrict__ fronts) {
+    extern __shared__ double lds_a[];
+    const int lane = threadIdx.x % 64, wv = threadIdx.x / 64, nw = blockDim.x / 64;
+    const int q = blockIdx.x * nw + wv;
+    if (q >= nt) return;
+    double* T = lds_a + (int64_t)wv * lda * lda;
+    int64_t* coff = reinterpret_cast<int64_t*>(lds_a + (int64_t)nw * lda * lda) + 64 * wv;
+    const int item = tile0 + q;
+    const int s = tile_sn[item];
+    const int m = mrows[s];
+    for (int e = lane; e < lda * lda; e += 64) T[e] = 0.0;
+    for (int64_t e = tile_kptr[item] + lane; e < tile_kptr[item + 1]; e += 64) {
+        const int pos = tile_kpos[e];  // position in a 64 x 64 tile
+        T[(pos % TB) + lda * (pos / TB)] = kval[tile_k[e]];
+    }
+    for (int64_t c4 = tile_cptr[item]; c4 < tile_cptr[item + 1]; c4++) {
+        const int32_t* rec = tile_crec + 5 * c4;
+        const int c = rec[0], ra = rec[1], rb = rec[2], ca = rec[3], cb = rec[4];
+        const int nc = ncol[c], mc = mrows[c];
+        const int32_t* rl = rel + rel_off[c];
+        const int nr = rb - ra, ncc = cb - ca;
+        if (lane < ncc) coff[lane] = foff[c] + fcol(mc, nc + ca + lane) + nc;
+        for (int e = lane; e < nr * ncc; e += 64) {
+            const int ui = ra + e % nr, uj = ca + e / nr;
+            if (ui >= uj) {
+                const double u = fronts[coff[uj - ca] + ui];
+                T[rl[ui] + lda * rl[uj]] += u;
+            }
+        }
+    }
+    double* F = fronts + foff[s];
+    for (int e = lane; e < m * m; e += 64) {
+        const int i = e % m, j = e / m;
+        if (i >= j) F[e] = T[i + lda * j];
     }
 }
 
@@ -1828,6 +1882,7 @@ static void build_numeric_plan(chol_sym* C, const std::vector<int32_t>& colptr, 
     }
     C->lvl_small_ptr.assign(nl + 1, 0);
     C->lvl_small.clear();
+    C->lvl_small_maxm.clear();
     C->lvl_narrow_ptr.assign(nl + 1, 0);
     C->lvl_narrow_maxm.clear();
     C->lvl_wide_ptr.assign(nl + 1, 0);
@@ -1883,6 +1938,11 @@ static void build_numeric_plan(chol_sym* C, const std::vector<int32_t>& colptr, 
                 }
         }
         C->lvl_small_ptr[l + 1] = (int32_t)C->lvl_small.size();
+        int mx = 1;
+        for (int q = C->lvl_small_ptr[l]; q < C->lvl_small_ptr[l + 1]; q++)
+            mx = std::max(mx, C->h_mrows[C->lvl_small[q]]);
+        const bool all_small = C->lvl_small_ptr[l + 1] - C->lvl_small_ptr[l] == C->lvl_ptr[l + 1] - C->lvl_ptr[l];
+        C->lvl_small_maxm.push_back(all_small ? mx : 0);
         C->asm_ptr[l + 1] = (int32_t)tsn.size();
     }
     // K entry (original numbering, lower CSC) -> tile and in-tile position
@@ -2461,9 +2521,19 @@ void chol_factor_enqueue(chol_sym* C, const double* kval, hipStream_t st, double
         int t0 = C->asm_ptr[l], t1 = C->asm_ptr[l + 1];
         if (t1 > t0) {
             tmark(C, st, 0);
-            hipLaunchKernelGGL(front_assemble, dim3(t1 - t0), dim3(NT), 0, st, t0, C->tile_sn.p, C->tile_rc.p,
-                               C->tile_kptr.p, C->tile_k.p, C->tile_kpos.p, kval, C->ncol.p, C->mrows.p, C->foff.p,
-                               C->tile_cptr.p, C->tile_crec.p, C->rel_off.p, C->rel.p, C->fronts.p);
+            const int lda = C->lvl_small_maxm[l];
+            if (lda > 0) {  // only fronts of at most 64 rows: one wave each, as many per work-group as 64 KB holds
+                const size_t per_front = (size_t)lda * lda * sizeof(double) + 64 * sizeof(int64_t);
+                const int per = std::max(1, std::min(NT / 64, (int)(65536 / per_front)));
+                hipLaunchKernelGGL(front_assemble_tiny, dim3(ceil_div(t1 - t0, per)), dim3(64 * per), per * per_front,
+                                   st, t0, t1 - t0, lda, C->tile_sn.p, C->tile_kptr.p, C->tile_k.p, C->tile_kpos.p,
+                                   kval, C->ncol.p, C->mrows.p, C->foff.p, C->tile_cptr.p, C->tile_crec.p,
+                                   C->rel_off.p, C->rel.p, C->fronts.p);
+            } else {
+                hipLaunchKernelGGL(front_assemble, dim3(t1 - t0), dim3(NT), 0, st, t0, C->tile_sn.p, C->tile_rc.p,
+                                   C->tile_kptr.p, C->tile_k.p, C->tile_kpos.p, kval, C->ncol.p, C->mrows.p,
+                                   C->foff.p, C->tile_cptr.p, C->tile_crec.p, C->rel_off.p, C->rel.p, C->fronts.p);
+            }
             OPF_LAUNCH_CHECK();
             tmark(C, st, 0);
         }
