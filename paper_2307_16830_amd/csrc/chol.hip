@@ -55,6 +55,7 @@ struct chol_sym {
     std::vector<int32_t> lvl_ptr, lvl_sn;           // supernodes by level
     std::vector<int32_t> lvl_small_ptr, lvl_small;  // fronts with m <= 64 by level
     std::vector<int32_t> lvl_small_maxm;            // largest of them, 0 when the level has larger fronts too
+    std::vector<int32_t> lvl_small_lda;             // largest of them
     std::vector<int32_t> lvl_narrow_ptr, lvl_narrow;  // fronts solved by one work-group, by level
     std::vector<int32_t> lvl_narrow_maxm;             // largest front of each level's list (<= 64: one-wave sweeps)
     // narrow fronts with many rows below their pivots ("tall"): the sweeps' products with those rows run as
@@ -335,12 +336,15 @@ __device__ __forceinline__ void lds_cholesky(double* A, int lda, int m, int ncol
     __syncthreads();
 }
 
+// The front in lda x lda doubles of dynamic LDS (lda = the level's largest front of at most 64 rows), so that
+// a compute unit holds as many of the leaf levels' small fronts as its wave slots allow.
 template <bool LDL>
 __global__ __launch_bounds__(NT) void front_small(const int32_t* __restrict__ list, const int32_t* __restrict__ first,
                                                   const int32_t* __restrict__ ncol, const int32_t* __restrict__ mrows,
                                                   const int64_t* __restrict__ foff, double* __restrict__ fronts,
-                                                  int32_t* __restrict__ status, PivotRef pr, double* __restrict__ dval) {
-    __shared__ double A[TB * TB];
+                                                  int32_t* __restrict__ status, PivotRef pr, double* __restrict__ dval,
+                                                  int lda) {
+    extern __shared__ double A[];
     __shared__ int bad;
     const int s = list[blockIdx.x];
     const int m = mrows[s], nn = ncol[s];
@@ -348,12 +352,12 @@ __global__ __launch_bounds__(NT) void front_small(const int32_t* __restrict__ li
     if (threadIdx.x == 0) bad = -1;
     for (int e = threadIdx.x; e < m * m; e += NT) {
         const int i = e % m, j = e / m;
-        if (i >= j) A[i + TB * j] = F[e];
+        if (i >= j) A[i + lda * j] = F[e];
     }
-    lds_cholesky<LDL>(A, TB, m, nn, &bad, pr, first[s], dval);
+    lds_cholesky<LDL>(A, lda, m, nn, &bad, pr, first[s], dval);
     for (int e = threadIdx.x; e < m * m; e += NT) {
         const int i = e % m, j = e / m;
-        if (i >= j) F[e] = A[i + TB * j];
+        if (i >= j) F[e] = A[i + lda * j];
     }
     if (threadIdx.x == 0) status[s] = bad >= 0 ? first[s] + bad : INT_MAX;
 }
@@ -1883,6 +1887,7 @@ static void build_numeric_plan(chol_sym* C, const std::vector<int32_t>& colptr, 
     C->lvl_small_ptr.assign(nl + 1, 0);
     C->lvl_small.clear();
     C->lvl_small_maxm.clear();
+    C->lvl_small_lda.clear();
     C->lvl_narrow_ptr.assign(nl + 1, 0);
     C->lvl_narrow_maxm.clear();
     C->lvl_wide_ptr.assign(nl + 1, 0);
@@ -1943,6 +1948,7 @@ static void build_numeric_plan(chol_sym* C, const std::vector<int32_t>& colptr, 
             mx = std::max(mx, C->h_mrows[C->lvl_small[q]]);
         const bool all_small = C->lvl_small_ptr[l + 1] - C->lvl_small_ptr[l] == C->lvl_ptr[l + 1] - C->lvl_ptr[l];
         C->lvl_small_maxm.push_back(all_small ? mx : 0);
+        C->lvl_small_lda.push_back(mx);
         C->asm_ptr[l + 1] = (int32_t)tsn.size();
     }
     // K entry (original numbering, lower CSC) -> tile and in-tile position
@@ -2540,9 +2546,10 @@ void chol_factor_enqueue(chol_sym* C, const double* kval, hipStream_t st, double
         int s0 = C->lvl_small_ptr[l], s1 = C->lvl_small_ptr[l + 1];
         if (s1 > s0) {
             tmark(C, st, 1);
-            hipLaunchKernelGGL(ldl ? front_small<true> : front_small<false>, dim3(s1 - s0), dim3(NT), 0, st,
-                               C->lvl_small_d.p + s0, C->first.p, C->ncol.p, C->mrows.p, C->foff.p, C->fronts.p,
-                               C->status.p, pr, C->dval.p);
+            const int lda = C->lvl_small_lda[l];
+            hipLaunchKernelGGL(ldl ? front_small<true> : front_small<false>, dim3(s1 - s0), dim3(NT),
+                               (size_t)lda * lda * sizeof(double), st, C->lvl_small_d.p + s0, C->first.p, C->ncol.p,
+                               C->mrows.p, C->foff.p, C->fronts.p, C->status.p, pr, C->dval.p, lda);
             OPF_LAUNCH_CHECK();
             tmark(C, st, 1);
         }
