@@ -263,7 +263,7 @@ def main():
                          "traffic for hardware-counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
+        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1"}), flush=True)
         sys.exit(2)
 
     sgrids = serving_grids(args.serving) if args.serving > 0 else None  # host work, before the GPU is touched
