@@ -414,9 +414,10 @@ typedef struct opf_server opf_server;
 void serve_default_options(serve_options* o);
 /* Allocates the pool and starts the workers on the current device. */
 int opf_serve_create(const serve_options* o, opf_server** out);
-/* Queue one request.  The model's host structure is built here (OPF_E_INVALID
- * for a bad grid, or for a tag already queued, running or holding a result);
- * admission and the solve happen on a worker. */
+/* Queue one request.  The grid is checked and copied here (OPF_E_INVALID for
+ * a bad grid, or for a tag already queued, running or holding a result); the
+ * model's host structure, the analysis, admission and the solve happen on a
+ * worker, so submissions do not wait for one another's host work. */
 int opf_serve_submit(opf_server* srv, const opf_grid* grid, int64_t tag);
 /* Up to ``max`` finished results (oldest first) into ``out``; *count receives
  * how many.  With wait != 0 the call blocks until at least one is ready or

@@ -2,7 +2,8 @@
 //
 // Worker slots, each a host thread with its own non-blocking HIP stream at the default priority, pull
 // requests in arrival order.  A slot first does the request's host work on its own (model structure,
-// symbolic analysis of the condensed pattern), so analyses of different requests run in parallel.  One
+// symbolic analysis of the condensed pattern), so the host work of different requests runs in parallel;
+// submission only checks and copies the grid.  One
 // device allocation (the pool) is carved into per-request regions: at admission a slot takes the largest
 // free block as a provisional region, creates the request's device buffers and IPM state inside it (every
 // DBuf of the calling thread is bump-allocated there), keeps exactly what was used (the request's
@@ -31,6 +32,9 @@
 using namespace opf;
 
 int ipm_prepare_device(ipm_state* S);  // ipm.hip: perform every pending device upload of a state now
+namespace opf {
+int validate_grid(const opf_grid* g);  // model.hip: the grid checks of opf_create
+}
 // ipm.hip: ipm_create with a prebuilt analysis (ownership passes) and a lent pinned buffer and events
 int ipm_create_ex(opf_model* M, const ipm_options* opts, const chol_options* copts, void* stream, chol_sym* prebuilt,
                   double* host, const hipEvent_t* events, ipm_state** out);
@@ -107,7 +111,7 @@ struct Request {
     int64_t tag = 0;
     double t_submit = 0;
     std::shared_ptr<GridCopy> grid;
-    opf_model* model = nullptr;  // built at submission; rebuilt after a failed admission
+    opf_model* model = nullptr;  // built by the worker that takes the request (again after a failed admission)
 };
 
 struct Done {
@@ -335,13 +339,13 @@ extern "C" int opf_serve_submit(opf_server* S, const opf_grid* grid, int64_t tag
         rq.tag = tag;
         rq.t_submit = now_s();
         rq.grid = std::make_shared<GridCopy>(*grid);
-        int rc = opf_create(&rq.grid->g, nullptr, nullptr, &rq.model);  // host structure only; uploads wait for admission
+        // only the grid's checks here: its model is built by the worker that takes it, in parallel with the
+        // other workers (building it here made every submission wait for the ones before it)
+        const int rc = validate_grid(&rq.grid->g);
         if (rc != OPF_OK) throw Error{rc};
         std::lock_guard<std::mutex> lk(S->mu);
-        if (S->done.count(tag) || S->active.count(tag)) {
-            opf_destroy(rq.model);
-            OPF_CHECK(false, OPF_E_INVALID, "opf_serve_submit: tag %lld is already in use", (long long)tag);
-        }
+        OPF_CHECK(!S->done.count(tag) && !S->active.count(tag), OPF_E_INVALID,
+                  "opf_serve_submit: tag %lld is already in use", (long long)tag);
         S->active.insert(tag);
         S->queue.push_back(std::move(rq));
         S->cv_work.notify_one();
