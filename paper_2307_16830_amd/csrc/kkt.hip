@@ -297,9 +297,9 @@ void build_kkt_maps(opf_model* M) {
     std::vector<int32_t> jt_ptr, jt_ent;
     csr_by_key(n, key, jt_ptr, jt_ent);
 
-    // candidate contributions to K entries: (col * n + row) keys
+    // candidate contributions to K entries, keyed by their (column, row) in the lower triangle
     struct Item {
-        int64_t key;
+        int32_t col, row;
         int32_t kind;  // 0 diag, 1 hessian entry, 2 jacobian pair
         int32_t a, b, r;
     };
@@ -310,9 +310,8 @@ void build_kkt_maps(opf_model* M) {
         npairs += len * (len + 1) / 2;
     }
     items.reserve(n + nh + npairs);
-    for (int i = 0; i < n; i++) items.push_back({(int64_t)i * n + i, 0, i, 0, 0});
-    for (int64_t e = 0; e < nh; e++)
-        items.push_back({(int64_t)M->hcol[e] * n + M->hrow[e], 1, (int32_t)e, 0, 0});
+    for (int i = 0; i < n; i++) items.push_back({i, i, 0, i, 0, 0});
+    for (int64_t e = 0; e < nh; e++) items.push_back({M->hcol[e], M->hrow[e], 1, (int32_t)e, 0, 0});
     for (int r = 0; r < m; r++) {
         for (int u = jr_ptr[r]; u < jr_ptr[r + 1]; u++) {
             int ea = jr_ent[u];
@@ -320,24 +319,47 @@ void build_kkt_maps(opf_model* M) {
                 int eb = jr_ent[v];
                 int ca = M->jcol[ea], cb = M->jcol[eb];
                 int hi = std::max(ca, cb), lo = std::min(ca, cb);
-                items.push_back({(int64_t)lo * n + hi, 2, ea, eb, r});
+                items.push_back({lo, hi, 2, ea, eb, r});
             }
         }
     }
-    std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) {
-        return x.key != y.key ? x.key < y.key : x.kind < y.kind;
-    });
+    // ordered by (column, row), equal keys by kind (the push order above: diagonal, Hessian entries, pairs):
+    // a stable bucketing by column, then each column's few items stably by row (a comparison sort of all the
+    // items, and then two scattering passes, dominated the model's host set-up)
+    {
+        std::vector<int64_t> cptr(n + 1, 0);
+        for (const Item& it : items) cptr[it.col + 1]++;
+        for (int i = 0; i < n; i++) cptr[i + 1] += cptr[i];
+        std::vector<Item> tmp(items.size());
+        {
+            std::vector<int64_t> fill(cptr.begin(), cptr.end() - 1);
+            for (const Item& it : items) tmp[fill[it.col]++] = it;
+        }
+        const auto by_row = [](const Item& x, const Item& y) { return x.row < y.row; };
+        for (int j = 0; j < n; j++) {
+            Item* b = tmp.data() + cptr[j];
+            Item* e = tmp.data() + cptr[j + 1];
+            if (e - b > 32) {
+                std::stable_sort(b, e, by_row);
+                continue;
+            }
+            for (Item* p = b + 1; p < e; p++)  // insertion sort: stable, no allocation
+                for (Item* q = p; q > b && by_row(q[0], q[-1]); q--) std::swap(q[0], q[-1]);
+        }
+        items.swap(tmp);
+    }
     std::vector<int32_t> colptr(n + 1, 0), rowind;
     std::vector<int32_t> hptr{0}, hidx, pptr{0}, pa, pb, pr, kdiag;
-    int64_t prev = -1;
+    int prow = -1, pcol = -1;
     for (const Item& it : items) {
-        if (it.key != prev) {
-            if (prev >= 0) {
+        if (it.col != pcol || it.row != prow) {
+            if (pcol >= 0) {
                 hptr.push_back((int32_t)hidx.size());
                 pptr.push_back((int32_t)pa.size());
             }
-            prev = it.key;
-            int col = (int)(it.key / n), row = (int)(it.key % n);
+            pcol = it.col;
+            prow = it.row;
+            const int col = it.col, row = it.row;
             rowind.push_back(row);
             colptr[col + 1]++;
             kdiag.push_back(row == col ? col : -1);
@@ -424,15 +446,17 @@ void build_kkt_maps(opf_model* M) {
         // K slots visited by the smallest constraint row among their Jacobian pair terms (ties by slot): the
         // slots of one row are adjacent, and consecutive rows of a template family read neighbouring J, D and
         // Hessian entries (the family-major layouts), instead of one random line per read
+        // (a stable counting sort: slots without pair terms take the last bucket, m)
         std::vector<int64_t> slot(nk);
-        std::vector<int32_t> key(nk);
+        std::vector<int32_t> key(nk), cnt(m + 2, 0);
         for (int64_t k = 0; k < nk; k++) {
-            slot[k] = k;
-            int32_t r = INT32_MAX;
+            int32_t r = m;
             for (int e = pptr[k]; e < pptr[k + 1]; e++) r = std::min(r, pr[e]);
             key[k] = r;
+            cnt[r + 1]++;
         }
-        std::stable_sort(slot.begin(), slot.end(), [&](int64_t a, int64_t b) { return key[a] < key[b]; });
+        for (int r = 0; r <= m; r++) cnt[r + 1] += cnt[r];
+        for (int64_t k = 0; k < nk; k++) slot[cnt[key[k]]++] = k;
         for (int64_t k : slot) {
             if (kdiag[k] >= 0) {
                 outs.push_back((int32_t)k);

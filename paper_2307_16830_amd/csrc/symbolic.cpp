@@ -117,22 +117,26 @@ std::vector<int32_t> min_degree_order(int n, const std::vector<int32_t>& colptr,
             el.push_back(v);
         }
         boundary[v] = Lp;
-        // exact degrees of the boundary variables
+        // exact degrees of the boundary variables: every one of them is adjacent to all of the new element's
+        // boundary (counted once, without u itself), plus whatever its other adjacencies add outside it.  The
+        // new boundary carries its own stamp, so one read of `seen` tells both "in the new boundary" and
+        // "already counted for u", and the count is branch-free (counting the new element per variable, with
+        // a data-dependent branch per entry, had made each step quadratic in the boundary size)
+        const int nL = (int)Lp.size();
+        const int stampL = ++stamp;
+        for (int u : Lp) seen[u] = stampL;
         for (int u : Lp) {
-            ++stamp;
-            int cnt = 0;
-            seen[u] = stamp;
-            for (int w : vadj[u])
-                if (seen[w] != stamp) {
-                    seen[w] = stamp;
-                    cnt++;
-                }
+            const int su = ++stamp;
+            int cnt = nL - 1;
+            auto visit = [&](int w) {
+                const int sw = seen[w];
+                cnt += (sw != su) & (sw != stampL);
+                seen[w] = sw == stampL ? stampL : su;
+            };
+            for (int w : vadj[u]) visit(w);
             for (int e : velem[u])
-                for (int w : boundary[e])
-                    if (seen[w] != stamp) {
-                        seen[w] = stamp;
-                        cnt++;
-                    }
+                if (e != v)
+                    for (int w : boundary[e]) visit(w);
             deg[u] = cnt;
             tree.set(u, cnt * W + u);
         }
