@@ -64,16 +64,41 @@ std::vector<int32_t> min_degree_order(int n, const std::vector<int32_t>& colptr,
         deg[v] = (int32_t)vadj[v].size();
         tree.set(v, deg[v] * W + v);
     }
-    std::vector<char> eliminated(n, 0), absorbed(n, 0);
+    std::vector<char> eliminated(n, 0), absorbed(n, 0), stale(n, 0);
     std::vector<int32_t> inL(n, -1), seen(n, -1);
     std::vector<int32_t> order;
     order.reserve(n);
     int remaining = n;
     int stamp = 0;
     std::vector<int32_t> Lp;
+    // Degrees are brought up to date lazily.  A variable next to a new element keeps a lower bound of its
+    // degree in the tree (eliminating a neighbour removes one neighbour and adds the rest of the new element's
+    // boundary, so the degree is at least max(old degree - 1, boundary size - 1)) and is marked stale; its
+    // exact degree is counted when it reaches the top of the tree.  The variable taken is therefore always the
+    // one of smallest (exact degree, index), as with every degree recounted after every elimination.
     while (remaining > 0) {
         int64_t key = tree.min();
         int v = (int)(key % W);
+        if (stale[v]) {
+            ++stamp;
+            int cnt = 0;
+            seen[v] = stamp;
+            auto visit = [&](int w) {
+                cnt += seen[w] != stamp;
+                seen[w] = stamp;
+            };
+            for (int w : vadj[v]) visit(w);
+            for (int e : velem[v])
+                for (int w : boundary[e]) visit(w);
+            deg[v] = cnt;
+            stale[v] = 0;
+            tree.set(v, cnt * W + v);
+            if (stamp > INT32_MAX - 4 * n) {
+                std::fill(seen.begin(), seen.end(), -1);
+                stamp = 0;
+            }
+            continue;
+        }
         int d = (int)(key / W);
         if ((double)d >= dense_frac * (double)(remaining - 1) || d >= dense_abs) {
             for (int u = 0; u < n; u++)
@@ -117,28 +142,12 @@ std::vector<int32_t> min_degree_order(int n, const std::vector<int32_t>& colptr,
             el.push_back(v);
         }
         boundary[v] = Lp;
-        // exact degrees of the boundary variables: every one of them is adjacent to all of the new element's
-        // boundary (counted once, without u itself), plus whatever its other adjacencies add outside it.  The
-        // new boundary carries its own stamp, so one read of `seen` tells both "in the new boundary" and
-        // "already counted for u", and the count is branch-free (counting the new element per variable, with
-        // a data-dependent branch per entry, had made each step quadratic in the boundary size)
+        // lower bounds for the boundary variables (exact counts when they reach the top)
         const int nL = (int)Lp.size();
-        const int stampL = ++stamp;
-        for (int u : Lp) seen[u] = stampL;
         for (int u : Lp) {
-            const int su = ++stamp;
-            int cnt = nL - 1;
-            auto visit = [&](int w) {
-                const int sw = seen[w];
-                cnt += (sw != su) & (sw != stampL);
-                seen[w] = sw == stampL ? stampL : su;
-            };
-            for (int w : vadj[u]) visit(w);
-            for (int e : velem[u])
-                if (e != v)
-                    for (int w : boundary[e]) visit(w);
-            deg[u] = cnt;
-            tree.set(u, cnt * W + u);
+            deg[u] = std::max(deg[u] - 1, nL - 1);
+            stale[u] = 1;
+            tree.set(u, deg[u] * W + u);
         }
         if (stamp > INT32_MAX - 4 * n) {
             std::fill(seen.begin(), seen.end(), -1);
