@@ -102,6 +102,73 @@ def test_symbolic_options_bit_exact(opts):
     assert np.array_equal(C.supernodes(), sym.snode_ptr)
 
 
+def random_pattern(rng, n):
+    """Lower CSC pattern (diagonal included) of a random symmetric graph: a few components, some dense rows,
+    isolated vertices and many equal degrees, so the ordering's tie-breaking and its dense cut are exercised."""
+    edges = set()
+    kind = rng.integers(4)
+    if kind == 0:  # sparse random graph
+        for _ in range(int(n * rng.uniform(0.5, 3.0))):
+            a, b = rng.integers(n, size=2)
+            edges.add((max(a, b), min(a, b)))
+    elif kind == 1:  # grid-like: a path plus chords, all degrees nearly equal
+        for i in range(1, n):
+            if rng.random() < 0.9:
+                edges.add((i, i - 1))
+        for _ in range(n // 4):
+            a, b = rng.integers(n, size=2)
+            edges.add((max(a, b), min(a, b)))
+    elif kind == 2:  # a few dense rows over a sparse background
+        for _ in range(n):
+            a, b = rng.integers(n, size=2)
+            edges.add((max(a, b), min(a, b)))
+        for h in rng.integers(n, size=3):
+            for j in rng.choice(n, size=n // 2, replace=False):
+                edges.add((max(h, j), min(h, j)))
+    else:  # disjoint cliques and stars
+        start = 0
+        while start < n:
+            size = int(rng.integers(1, 9))
+            block = range(start, min(n, start + size))
+            for a in block:
+                for b in block:
+                    if a > b and (rng.random() < 0.7 or b == start):
+                        edges.add((a, b))
+            start += size
+    cols = [[j] for j in range(n)]
+    for a, b in edges:
+        if a != b:
+            cols[b].append(a)
+    cp = np.zeros(n + 1, dtype=np.int32)
+    ri = []
+    for j in range(n):
+        c = sorted(set(cols[j]))
+        ri.extend(c)
+        cp[j + 1] = cp[j] + len(c)
+    return cp, np.array(ri, dtype=np.int32)
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_symbolic_bit_exact_on_random_patterns(seed):
+    """Exact minimum degree (degrees recounted lazily from lower bounds), etree, column counts and supernodes
+    against the oracle's explicit elimination-graph ordering and column-union symbolic factorization."""
+    rng = np.random.default_rng(1000 + seed)
+    n = int(rng.integers(1, 160))
+    cp, ri = random_pattern(rng, n)
+    o = dict(OPTS)
+    if seed % 3 == 1:
+        o.update(dense_frac=0.3)
+    if seed % 3 == 2:
+        o.update(dense_abs=int(rng.integers(2, 12)), zero_abs=0, zero_rel=0.0)
+    C = opf().Cholesky(n, cp, ri, opf().chol_options(**o))
+    sym = ochol.analyze(n, cp, ri, ochol.AnalyzeOptions(**o))
+    assert np.array_equal(C.perm(), sym.perm)
+    par, cc = C.etree()
+    assert np.array_equal(par, sym.parent)
+    assert np.array_equal(cc, sym.colcount)
+    assert np.array_equal(C.supernodes(), sym.snode_ptr)
+
+
 def test_chol_analyze_rejects_bad_patterns():
     O = opf()
     with pytest.raises(O.OpfError):
