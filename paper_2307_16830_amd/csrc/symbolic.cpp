@@ -14,7 +14,9 @@
 //     <= zero_rel of its stored entries.
 // The elimination graph is kept as a quotient graph: eliminated vertices
 // become elements holding their boundary; a variable's degree is the size of
-// the union of its variable neighbours and its elements' boundaries.
+// the union of its variable neighbours and its elements' boundaries, counted
+// when the variable reaches the top of the priority tree (a variable whose
+// neighbourhood changed waits there under a lower bound of its degree).
 #include "symbolic.h"
 
 #include <algorithm>
