@@ -503,34 +503,34 @@ namespace opf {
 // server to reject a bad grid at submission without building the model there.
 static void check_grid(const opf_grid* g) {
     OPF_CHECK(g->nbus >= 1 && g->nbranch >= 0 && g->ngen >= 1, OPF_E_INVALID,
-              "opf_create: need nbus >= 1, nbranch >= 0, ngen >= 1");
-    OPF_CHECK(g->ref_bus >= 0 && g->ref_bus < g->nbus, OPF_E_INVALID, "opf_create: ref_bus out of range");
-    OPF_CHECK(g->base_mva > 0, OPF_E_INVALID, "opf_create: base_mva must be positive");
+              "invalid grid: need nbus >= 1, nbranch >= 0, ngen >= 1");
+    OPF_CHECK(g->ref_bus >= 0 && g->ref_bus < g->nbus, OPF_E_INVALID, "invalid grid: ref_bus out of range");
+    OPF_CHECK(g->base_mva > 0, OPF_E_INVALID, "invalid grid: base_mva must be positive");
     const int64_t N = g->nbus, E = g->nbranch, G = g->ngen;
     OPF_CHECK(2 * N + 2 * G + 4 * E < INT32_MAX && 2 * N + 1 + 7 * E < INT32_MAX, OPF_E_INVALID,
-              "opf_create: problem too large for int32 indices");
+              "invalid grid: problem too large for int32 indices");
     for (int64_t l = 0; l < E; l++) {
         OPF_CHECK(g->f[l] >= 0 && g->f[l] < N && g->t[l] >= 0 && g->t[l] < N && g->f[l] != g->t[l],
-                  OPF_E_INVALID, "opf_create: branch %lld has invalid endpoints", (long long)l);
+                  OPF_E_INVALID, "invalid grid: branch %lld has invalid endpoints", (long long)l);
         OPF_CHECK(g->r[l] * g->r[l] + g->x[l] * g->x[l] > 0, OPF_E_INVALID,
-                  "opf_create: branch %lld has zero impedance", (long long)l);
-        OPF_CHECK(g->rate[l] > 0, OPF_E_INVALID, "opf_create: branch %lld has non-positive rating",
+                  "invalid grid: branch %lld has zero impedance", (long long)l);
+        OPF_CHECK(g->rate[l] > 0, OPF_E_INVALID, "invalid grid: branch %lld has non-positive rating",
                   (long long)l);
     }
     for (int64_t k = 0; k < G; k++) {
-        OPF_CHECK(g->gbus[k] >= 0 && g->gbus[k] < N, OPF_E_INVALID, "opf_create: generator %lld bus",
+        OPF_CHECK(g->gbus[k] >= 0 && g->gbus[k] < N, OPF_E_INVALID, "invalid grid: generator %lld bus",
                   (long long)k);
         OPF_CHECK(g->pmin[k] <= g->pmax[k] && g->qmin[k] <= g->qmax[k], OPF_E_INVALID,
-                  "opf_create: generator %lld has inverted limits", (long long)k);
+                  "invalid grid: generator %lld has inverted limits", (long long)k);
     }
     for (int64_t i = 0; i < N; i++)
-        OPF_CHECK(g->vmin[i] <= g->vmax[i] && g->vmin[i] > 0, OPF_E_INVALID, "opf_create: bus %lld vm bounds",
+        OPF_CHECK(g->vmin[i] <= g->vmax[i] && g->vmin[i] > 0, OPF_E_INVALID, "invalid grid: bus %lld vm bounds",
                   (long long)i);
 }
 
 int validate_grid(const opf_grid* g) {
     return guarded([&] {
-        OPF_CHECK(g, OPF_E_INVALID, "opf_create: null argument");
+        OPF_CHECK(g, OPF_E_INVALID, "invalid grid: null pointer");
         check_grid(g);
     });
 }
