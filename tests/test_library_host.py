@@ -45,6 +45,44 @@ def test_invalid_grid_is_rejected():
     assert e.value.code == opf().E_INVALID
 
 
+def _break(g, what):
+    if what == "self_loop":
+        g.t[1] = g.f[1]
+    elif what == "to_out_of_range":
+        g.t[2] = -1
+    elif what == "zero_impedance":
+        g.r[0] = 0.0
+        g.x[0] = 0.0
+    elif what == "rating":
+        g.rate[3] = 0.0
+    elif what == "gen_bus":
+        g.gbus[0] = len(g.pd)
+    elif what == "gen_limits":
+        g.pmin[1] = g.pmax[1] + 1.0
+    elif what == "vm_bounds":
+        g.vmin[4] = g.vmax[4] + 0.01
+    elif what == "vm_zero":
+        g.vmin[0] = 0.0
+    elif what == "ref_bus":
+        g.ref_bus = len(g.pd)
+    elif what == "base_mva":
+        g.base_mva = 0.0
+
+
+@pytest.mark.parametrize("what", ["self_loop", "to_out_of_range", "zero_impedance", "rating", "gen_bus",
+                                  "gen_limits", "vm_bounds", "vm_zero", "ref_bus", "base_mva"])
+def test_each_grid_check_rejects(what):
+    """Every grid check (shared by opf_create and the solve server's submission) turns its bad input into
+    E_INVALID with a message naming the problem, and the unbroken grid is accepted."""
+    g = gridgen.make_grid(8, 10, 3, 2)
+    opf().Model(g)
+    _break(g, what)
+    with pytest.raises(opf().OpfError) as e:
+        opf().Model(g)
+    assert e.value.code == opf().E_INVALID
+    assert "invalid grid" in str(e.value)
+
+
 @pytest.mark.parametrize("case", ["cfg0", (40, 55, 8, 3), "cfg1"])
 def test_host_structure_and_symbolic_match_oracle(case):
     g = gridgen.make_config(case) if isinstance(case, str) else gridgen.make_grid(*case)
